@@ -1,0 +1,145 @@
+/*
+ * crfrob -- controlled reduction of hypersurface zeta functions on AMD MI355X.
+ *
+ * C ABI of libcrfrob.so.  Plain pointers and sizes only; every call returns a
+ * cr_status (0 = CR_OK) and never throws.  On error the outputs of the failing
+ * item are left untouched and cr_last_error() describes the failure.
+ *
+ * Mathematics (arXiv 2602.24155): X = V(f) a smooth hypersurface of degree d
+ * in P^n over F_p, 7 <= p < 50.  Its zeta function is
+ *   Z(X,T) = Q(T)^((-1)^n) / prod_{i<n} (1 - p^i T)            (Section 2.1)
+ * with Q(T) = det(1 - T Phi), Phi the matrix of p^{-1} sigma on H^n_dR(U) in
+ * the monomial basis of Section 2.3.  The library returns the matrix Phi'
+ * whose column c holds the coordinates of p^(m_c - n - 1) sigma(x^beta Omega
+ * / f^m_c) (Proposition 2.1), so Phi = Phi' diag(p^(n - m_c)), and the
+ * integer coefficients of Q(T).
+ *
+ * Conventions shared by every entry point:
+ *  - nvars = n + 1 variables, 3 <= nvars <= 6; degree d >= 2.
+ *  - Coefficients are listed in lexicographically DESCENDING order of the
+ *    exponent vectors of the degree-d monomials (x_0^d first; cr_monomials
+ *    returns that list) and are the representatives in [0, p) of the F_p
+ *    coefficients; this integer polynomial is the lift f of Section 2.1.
+ *  - Basis of H^n_dR(U): for m = 1..n the degree dm-n-1 monomials that are
+ *    not pivot columns of the row-echelon form (mod p) of the image of
+ *    (mu_i) -> sum mu_i d_i f, monomials scanned in the order above
+ *    (Section 2.3).  Basis elements are ordered by m, then by that order.
+ *  - Precision (Section 2.5): one relative precision r for all columns, the
+ *    smallest that recovers every a_i (i <= b/2) of Q(T) from the Weil bound
+ *    either directly (a_i mod p^(r + h_i)) or through the power sum
+ *    tr(Phi^i); series order N_m = r + 1; working modulus p^M with
+ *    M = max_m (r + v_p((p s_m - 1)!) - m + 1), s_m = N_m + m - 1.
+ *  - The Frobenius series coefficients D_{j,m} C_{j,alpha} of Proposition 2.1
+ *    are taken exactly and reduced mod p^M.
+ */
+#ifndef CRFROB_H
+#define CRFROB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CR_OK = 0,
+    CR_EINVAL = 1,        /* bad sizes / null pointers / unsupported nvars, degree */
+    CR_ENOTPRIME = 2,     /* p is not prime */
+    CR_EPRANGE = 3,       /* need 7 <= p < 50, p > n, p not dividing d */
+    CR_ESINGULAR = 4,     /* f mod p is singular (Jacobian criterion) */
+    CR_ENOT_S_SMOOTH = 5, /* f is smooth but not S-smooth for the requested S (Definition 3.1) */
+    CR_EPRECISION = 6,    /* p^M does not fit the 64-bit residues of this build */
+    CR_ENOMEM = 7,        /* host or device allocation failed */
+    CR_EDEVICE = 8,       /* HIP runtime error, or no gfx950 device */
+    CR_ESELFCHECK = 9     /* a built-in consistency check failed (divisibility of a
+                             column, det Phi' = +-1 mod p, integrality of Newton's identities) */
+} cr_status;
+
+/* Reduction policies (Section 4).  Every policy yields the same Phi' bits:
+ * each reduction step is an exact identity in cohomology and the
+ * coordinates of a class are unique. */
+typedef enum {
+    CR_POLICY_DEPTH_FIRST = 0 /* Section 4.2: per term greedy v (Algorithm 3), largest chunk k
+                                 with v in V_full(u, k); never combines like terms */
+} cr_policy;
+
+/* A family of hypersurfaces that share nvars, degree and S; p may vary per item. */
+typedef struct {
+    int32_t nvars;    /* n + 1 */
+    int32_t degree;   /* d */
+    uint32_t s_mask;  /* S of Definition 3.1 as a bit set over x_0..x_n; 0 = all variables */
+    int32_t policy;   /* cr_policy */
+    int32_t r;        /* relative precision override; 0 = derive (header comment) */
+    int32_t n_series; /* series order override N_m for every m; 0 = r + 1 */
+} cr_family;
+
+/* Per-call statistics (all counts are summed over the batch). */
+typedef struct {
+    int64_t start_blocks;  /* distinct Frobenius start terms (x^S form exponents) */
+    int64_t column_steps;  /* s x s . s reduction products (the paper's unit M of Section 3.4) */
+    int64_t chunks;        /* reduction chunks (u, v, k) */
+    double setup_ms;       /* host setup wall time */
+    double device_ms;      /* device time of the reduction and assembly kernels */
+    double finish_ms;      /* host unscaling and L-polynomial recovery */
+} cr_stats;
+
+/* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},
+ * Proposition 3.3); b = dimension of H^n_dR(U) (side of Phi').  Pure function
+ * of (nvars, degree); outputs may be NULL. */
+cr_status cr_query_dims(int32_t nvars, int32_t degree, int32_t *ncoeff, int32_t *s, int32_t *b);
+
+/* Exponent vectors of the degree-d monomials in coefficient order:
+ * exps[k * nvars + i] = exponent of x_i in monomial k.  Caller-owned, ncoeff*nvars. */
+cr_status cr_monomials(int32_t nvars, int32_t degree, int32_t *exps);
+
+/* Precision chosen for prime p (header comment): r, N (= N_m for every m) and
+ * M.  Outputs may be NULL. */
+cr_status cr_precision(const cr_family *fam, int32_t p, int32_t *r, int32_t *n_series, int32_t *M);
+
+/* 1 in *smooth iff f mod p is smooth (and S-smooth for fam->s_mask); the
+ * status is CR_OK either way for valid arguments. */
+cr_status cr_check_smooth(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t *smooth);
+
+/*
+ * Frobenius matrices and L-polynomials of `count` hypersurfaces of one family
+ * (Sections 2-4): host setup (Section 2.3-2.5, Proposition 2.1, decomposition
+ * map of Proposition 3.3, Griffiths-Dwork map of Section 3.3), one batched
+ * device reduction of every start term to pole order n (Proposition 3.3 with
+ * the explicit R_{u,v} of Section 3.1, Algorithm 2 order of evaluation), the
+ * device Griffiths-Dwork assembly, host unscaling and Q(T).
+ *
+ *   primes     [count]            p of each item
+ *   coeffs     [count * ncoeff]   coefficients in [0, p), cr_monomials order
+ *   frob       [count * b * b]    Phi' residues, row-major; column c is known
+ *                                 mod p^col_prec[c]
+ *   frob_scaled[count * b * b]    may be NULL: the coordinates before unscaling,
+ *                                 exact mod p^M (the quantity every reduction
+ *                                 policy reproduces bit for bit)
+ *   col_pole   [count * b]        pole order m of each column
+ *   col_prec   [count * b]        p-adic digits known in each column of Phi'
+ *   lpoly      [count * (b+1) * 4] Q(T) coefficients a_0..a_b, each a signed
+ *                                 256-bit two's-complement integer as four
+ *                                 little-endian uint64 words; a_0 = 1
+ *   item_status[count]            per-item cr_status (may be NULL)
+ *   stats      may be NULL
+ *   hip_stream hipStream_t of the caller, or NULL for the default stream
+ * All buffers are host memory owned by the caller.  Device memory is owned by
+ * the library (kept across calls and reused) and freed by cr_release().
+ * Returns CR_OK if every item succeeded, else the first failing item's status.
+ */
+cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t *primes,
+                             const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
+                             int32_t *col_pole, int32_t *col_prec, int64_t *lpoly,
+                             int32_t *item_status, cr_stats *stats, void *hip_stream);
+
+/* Frees the library's cached device and host workspaces. */
+cr_status cr_release(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *cr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRFROB_H */

@@ -1,0 +1,145 @@
+"""ctypes binding of libcrfrob.so (same names as include/crfrob.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's host C++ and HIP kernels.  Loading fails loudly if the library is
+missing; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrfrob.so")
+
+CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
+    CR_EPRECISION, CR_ENOMEM, CR_EDEVICE, CR_ESELFCHECK = range(10)
+CR_POLICY_DEPTH_FIRST = 0
+
+EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
+           "cr_frobenius_batch", "cr_release", "cr_last_error"]
+
+
+class cr_family(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
+                ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32)]
+
+
+class cr_stats(ctypes.Structure):
+    _fields_ = [("start_blocks", ctypes.c_int64), ("column_steps", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
+
+
+class CrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("crfrob status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcrfrob.so is not built (run __graft_entry__.build()): %s" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        i32, u32, u64, i64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
+        L.cr_query_dims.argtypes = [i32, i32, P(i32), P(i32), P(i32)]
+        L.cr_monomials.argtypes = [i32, i32, P(i32)]
+        L.cr_precision.argtypes = [P(cr_family), i32, P(i32), P(i32), P(i32)]
+        L.cr_check_smooth.argtypes = [P(cr_family), i32, P(u32), P(i32)]
+        L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
+                                         P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
+        L.cr_release.argtypes = []
+        L.cr_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "cr_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != CR_OK:
+        raise CrError(st, lib().cr_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0):
+    return cr_family(nvars, degree, s_mask, policy, r, n_series)
+
+
+def cr_query_dims(nvars, degree):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cr_query_dims(nvars, degree, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def cr_monomials(nvars, degree):
+    nco = cr_query_dims(nvars, degree)[0]
+    out = np.zeros((nco, nvars), dtype=np.int32)
+    _check(lib().cr_monomials(nvars, degree, _ptr(out, ctypes.c_int32)))
+    return out
+
+
+def cr_precision(fam, p):
+    r, N, M = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cr_precision(ctypes.byref(fam), p, ctypes.byref(r), ctypes.byref(N), ctypes.byref(M)))
+    return r.value, N.value, M.value
+
+
+def cr_check_smooth(fam, p, coeffs):
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32))
+    out = ctypes.c_int32()
+    _check(lib().cr_check_smooth(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), ctypes.byref(out)))
+    return bool(out.value)
+
+
+def _lpoly_ints(words):
+    out = []
+    for k in range(words.shape[0]):
+        x = 0
+        for j in range(4):
+            x |= int(np.uint64(words[k, j])) << (64 * j)
+        if x >> 255:
+            x -= 1 << 256
+        out.append(x)
+    return out
+
+
+def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise_on_error=True):
+    """Run the whole path for a batch; returns a dict of numpy arrays / lists."""
+    primes = np.ascontiguousarray(np.asarray(primes, dtype=np.int32))
+    count = int(primes.shape[0])
+    nco, _s, b = cr_query_dims(fam.nvars, fam.degree)
+    co = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32).reshape(count, nco))
+    frob = np.zeros((count, b, b), dtype=np.uint64)
+    scaled = np.zeros((count, b, b), dtype=np.uint64) if want_scaled else None
+    pole = np.zeros((count, b), dtype=np.int32)
+    prec = np.zeros((count, b), dtype=np.int32)
+    lp = np.zeros((count, b + 1, 4), dtype=np.int64)
+    ist = np.zeros(count, dtype=np.int32)
+    stats = cr_stats()
+    st = lib().cr_frobenius_batch(ctypes.byref(fam), count, _ptr(primes, ctypes.c_int32),
+                                  _ptr(co, ctypes.c_uint32), _ptr(frob, ctypes.c_uint64),
+                                  _ptr(scaled, ctypes.c_uint64) if scaled is not None else None,
+                                  _ptr(pole, ctypes.c_int32), _ptr(prec, ctypes.c_int32),
+                                  _ptr(lp, ctypes.c_int64), _ptr(ist, ctypes.c_int32),
+                                  ctypes.byref(stats), ctypes.c_void_p(stream or 0))
+    if raise_on_error:
+        _check(st)
+    return {
+        "status": st, "item_status": ist, "frob": frob, "scaled": scaled, "col_pole": pole,
+        "col_prec": prec, "lpoly": [_lpoly_ints(lp[i]) for i in range(count)], "stats": stats,
+    }
+
+
+def cr_release():
+    _check(lib().cr_release())

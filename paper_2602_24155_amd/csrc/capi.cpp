@@ -1,0 +1,434 @@
+// C-ABI entry points of libcrfrob.so (declared in include/crfrob.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "device_layout.hpp"
+#include "host.hpp"
+
+namespace crf {
+size_t reduce_lds_bytes(const DevFamily &fam, int ct);
+hipError_t launch_reduce(const DevFamily &fam, const DevItem *items, const DevTile *tiles, int ntiles,
+                         const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int ct,
+                         int *err, hipStream_t stream);
+hipError_t launch_assemble(const DevFamily &fam, const DevItem *items, int nitems, const uint64_t *hbuf,
+                           hipStream_t stream);
+}  // namespace crf
+
+using namespace crf;
+
+namespace {
+
+thread_local std::string g_err;
+
+cr_status fail(cr_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+// ------------------------------------------------------------ device memory
+// One grow-only device buffer and one pinned host staging buffer, reused by
+// every call (calls are serialised by g_mutex).
+struct Arena {
+    void *dev = nullptr;
+    size_t dev_cap = 0;
+    void *host = nullptr;
+    size_t host_cap = 0;
+    bool ensure(size_t dbytes, size_t hbytes) {
+        if (dbytes > dev_cap) {
+            if (dev) (void)hipFree(dev);
+            dev = nullptr;
+            dev_cap = 0;
+            size_t cap = std::max(dbytes, dev_cap * 2);
+            if (hipMalloc(&dev, cap) != hipSuccess) return false;
+            dev_cap = cap;
+        }
+        if (hbytes > host_cap) {
+            if (host) (void)hipHostFree(host);
+            host = nullptr;
+            host_cap = 0;
+            size_t cap = std::max(hbytes, host_cap * 2);
+            if (hipHostMalloc(&host, cap, hipHostMallocDefault) != hipSuccess) return false;
+            host_cap = cap;
+        }
+        return true;
+    }
+    void release() {
+        if (dev) (void)hipFree(dev);
+        if (host) (void)hipHostFree(host);
+        dev = host = nullptr;
+        dev_cap = host_cap = 0;
+    }
+};
+
+struct FamilyEntry {
+    Family fam;
+    std::vector<unsigned char> tables;  // packed device tables (host copy)
+    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU;
+};
+
+std::mutex g_mutex;
+Arena g_arena;
+std::map<std::tuple<int, int, uint32_t>, std::unique_ptr<FamilyEntry>> g_families;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+FamilyEntry *get_family(const cr_family *fam, std::string &err) {
+    auto key = std::make_tuple(fam->nvars, fam->degree, fam->s_mask);
+    auto it = g_families.find(key);
+    if (it != g_families.end()) return it->second.get();
+    auto e = std::make_unique<FamilyEntry>();
+    if (!e->fam.init(fam->nvars, fam->degree, fam->s_mask, err)) return nullptr;
+    const Family &F = e->fam;
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        e->tables.resize(off);
+        std::memcpy(e->tables.data() + at, src, bytes);
+        return at;
+    };
+    e->off_colmap = put(F.colmap.data(), F.colmap.size() * 2);
+    e->off_gsrc = put(F.gsrc.data(), F.gsrc.size() * 2);
+    e->off_gw = put(F.gw.data(), F.gw.size() * 2);
+    e->off_finmap = put(F.finmap.data(), F.finmap.size() * 2);
+    e->off_dirs = put(F.dirs.exps.data(), F.dirs.exps.size());
+    e->off_finU = put(F.finU.exps.data(), std::max<size_t>(F.finU.exps.size(), 1));
+    auto *raw = e.get();
+    g_families.emplace(key, std::move(e));
+    return raw;
+}
+
+template <class Fn>
+void parallel_for(int count, Fn fn) {
+    int hw = (int)std::thread::hardware_concurrency();
+    int nt = std::max(1, std::min({count, hw > 0 ? hw : 1, 16}));
+    if (nt == 1) {
+        for (int i = 0; i < count; i++) fn(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; t++)
+        th.emplace_back([&]() {
+            for (int i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+long long hodge_size(int nv, int d, int m) {
+    const int n = nv - 1, k = d * m - n - 1;
+    long long h = 0;
+    for (int j = 0; j < nv; j++) {
+        int kk = k - j * (d - 1);
+        if (kk < 0) break;
+        h += ((j & 1) ? -1 : 1) * binom(nv, j) * count_monomials(nv, kk);
+    }
+    return h;
+}
+
+bool check_family(const cr_family *fam, std::string &err) {
+    if (!fam) {
+        err = "null family";
+        return false;
+    }
+    if (fam->nvars < 3 || fam->nvars > kMaxVars || fam->degree < 2 || fam->degree > 12) {
+        err = "unsupported nvars/degree";
+        return false;
+    }
+    if (fam->policy != CR_POLICY_DEPTH_FIRST) {
+        err = "unknown policy";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cr_last_error(void) { return g_err.c_str(); }
+
+cr_status cr_query_dims(int32_t nvars, int32_t degree, int32_t *ncoeff, int32_t *s, int32_t *b) {
+    if (nvars < 3 || nvars > kMaxVars || degree < 2) return fail(CR_EINVAL, "unsupported nvars/degree");
+    const int n = nvars - 1;
+    if (ncoeff) *ncoeff = (int32_t)count_monomials(nvars, degree);
+    if (s) *s = (int32_t)count_monomials(nvars, degree * n - n);
+    if (b) {
+        long long t = 0;
+        for (int m = 1; m <= n; m++) t += hodge_size(nvars, degree, m);
+        *b = (int32_t)t;
+    }
+    return CR_OK;
+}
+
+cr_status cr_monomials(int32_t nvars, int32_t degree, int32_t *exps) {
+    if (nvars < 3 || nvars > kMaxVars || degree < 2 || !exps) return fail(CR_EINVAL, "bad arguments");
+    MonoSpace sp;
+    sp.init(nvars, degree);
+    for (size_t k = 0; k < sp.exps.size(); k++) exps[k] = sp.exps[k];
+    return CR_OK;
+}
+
+cr_status cr_precision(const cr_family *fam, int32_t p, int32_t *r, int32_t *n_series, int32_t *M) {
+    std::string err;
+    if (!check_family(fam, err)) return fail(CR_EINVAL, err);
+    const int n = fam->nvars - 1;
+    std::vector<int> hodge(n);
+    for (int m = 1; m <= n; m++) hodge[m - 1] = (int)hodge_size(fam->nvars, fam->degree, m);
+    int rr, NN, MM;
+    if (!choose_precision(p, n, hodge, fam->r, fam->n_series, rr, NN, MM, err)) return fail(CR_EINVAL, err);
+    if (r) *r = rr;
+    if (n_series) *n_series = NN;
+    if (M) *M = MM;
+    return CR_OK;
+}
+
+cr_status cr_check_smooth(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t *smooth) {
+    std::string err;
+    if (!check_family(fam, err) || !coeffs || !smooth) return fail(CR_EINVAL, err.empty() ? "null pointer" : err);
+    FamilyEntry *fe;
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        fe = get_family(fam, err);
+    }
+    if (!fe) return fail(CR_EINVAL, err);
+    ItemSetup it;
+    cr_status st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err, true);
+    if (st == CR_ESINGULAR || st == CR_ENOT_S_SMOOTH) {
+        *smooth = 0;
+        return CR_OK;
+    }
+    if (st != CR_OK) return fail(st, err);
+    *smooth = 1;
+    return CR_OK;
+}
+
+cr_status cr_release(void) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    g_arena.release();
+    return CR_OK;
+}
+
+cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
+                             uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole, int32_t *col_prec,
+                             int64_t *lpoly, int32_t *item_status, cr_stats *stats, void *hip_stream) {
+    std::string err;
+    if (!check_family(fam, err)) return fail(CR_EINVAL, err);
+    if (count < 0 || (count > 0 && (!primes || !coeffs || !frob || !col_pole || !col_prec || !lpoly)))
+        return fail(CR_EINVAL, "null output or input pointer");
+    if (count == 0) return CR_OK;
+    std::lock_guard<std::mutex> lk(g_mutex);
+    FamilyEntry *fe = get_family(fam, err);
+    if (!fe) return fail(CR_EINVAL, err);
+    const Family &F = fe->fam;
+    int32_t nco, s_dim, b;
+    cr_query_dims(fam->nvars, fam->degree, &nco, &s_dim, &b);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto t0 = std::chrono::steady_clock::now();
+
+    // ---- host setup, one item per task
+    std::vector<ItemSetup> items(count);
+    std::vector<cr_status> st(count, CR_OK);
+    std::vector<std::string> errs(count);
+    parallel_for(count, [&](int i) {
+        st[i] = setup_item(F, primes[i], coeffs + (size_t)i * nco, fam->r, fam->n_series, items[i], errs[i]);
+        if (st[i] == CR_OK && items[i].b != b) {
+            st[i] = CR_ESELFCHECK;
+            errs[i] = "basis size differs from the Hodge numbers";
+        }
+    });
+    const double setup_ms = ms_since(t0);
+
+    // ---- pack device buffers
+    std::vector<int> live;
+    for (int i = 0; i < count; i++)
+        if (st[i] == CR_OK) live.push_back(i);
+    const int nlive = (int)live.size();
+    if (nlive == 0) {
+        cr_status first = CR_OK;
+        for (int i = 0; i < count; i++) {
+            if (item_status) item_status[i] = st[i];
+            if (first == CR_OK) {
+                first = st[i];
+                g_err = "item " + std::to_string(i) + ": " + errs[i];
+            }
+        }
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->setup_ms = setup_ms;
+        }
+        return first;
+    }
+    size_t nchain = 0, psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
+    for (int i : live) nchain += items[i].nchain();
+    // choose chains per workgroup so the LDS tile stays within 64 KiB
+    DevFamily df{};
+    df.nv = F.nv;
+    df.n = F.n;
+    df.d = F.d;
+    df.smask = F.smask;
+    df.s = F.g.count;
+    df.T = F.tgt.count;
+    df.nsrc = F.nsrc;
+    df.F = F.fin.count;
+    df.ndir = F.dirs.count;
+    df.nfinU = F.finU.count;
+    int ct = 32;
+    while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
+    if (reduce_lds_bytes(df, ct) > 64 * 1024) return fail(CR_EINVAL, "family too large for the LDS tile");
+    std::vector<DevTile> tiles;
+    for (int li = 0; li < nlive; li++) {
+        const ItemSetup &it = items[live[li]];
+        for (int c0 = 0; c0 < it.nchain(); c0 += ct) {
+            DevTile t{};
+            t.item = li;
+            t.count = std::min(ct, it.nchain() - c0);
+            t.chain0 = c0;  // item-relative for now
+            t.steps = it.chain_pole[c0] - F.n;
+            tiles.push_back(t);
+        }
+    }
+    // device layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const size_t o_tables = take(fe->tables.size());
+    const size_t o_items = take(sizeof(DevItem) * std::max(nlive, 1));
+    const size_t o_tiles = take(sizeof(DevTile) * std::max<size_t>(tiles.size(), 1));
+    const size_t o_psi = take(8 * psi_len * nlive);
+    const size_t o_rho = take(8 * rho_len * nlive);
+    const size_t o_coef = take(8 * (size_t)b * nchain);
+    const size_t o_cu = take(2 * (size_t)F.nv * nchain);
+    const size_t o_cg = take(4 * nchain);
+    const size_t o_cp = take(4 * nchain);
+    const size_t o_err = take(4);
+    const size_t h_end = off;  // everything above is uploaded
+    const size_t o_Y = take(8 * (size_t)b * b * nlive);
+    const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
+    const size_t o_hbuf = take(8 * (size_t)F.fin.count * nchain);
+    const size_t d_end = off;
+    if (!g_arena.ensure(d_end, d_end)) return fail(CR_ENOMEM, "device or pinned host allocation failed");
+    unsigned char *hb = static_cast<unsigned char *>(g_arena.host);
+    unsigned char *db = static_cast<unsigned char *>(g_arena.dev);
+    std::memcpy(hb + o_tables, fe->tables.data(), fe->tables.size());
+    df.colmap = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_colmap);
+    df.gsrc = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_gsrc);
+    df.gw = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_gw);
+    df.finmap = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_finmap);
+    df.dirs = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_dirs);
+    df.finU = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_finU);
+    DevItem *hitems = reinterpret_cast<DevItem *>(hb + o_items);
+    size_t chain_at = 0;
+    std::vector<size_t> item_chain0(nlive);
+    for (int li = 0; li < nlive; li++) {
+        const ItemSetup &it = items[live[li]];
+        DevItem &di = hitems[li];
+        di.q = it.mq.q;
+        di.mu = it.mq.mu;
+        di.sbits = it.mq.sbits;
+        di.b = b;
+        di.chain0 = (int32_t)chain_at;
+        di.nchain = it.nchain();
+        di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
+        di.rho = reinterpret_cast<const uint64_t *>(db + o_rho) + rho_len * li;
+        di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + (size_t)b * chain_at;
+        di.Y = reinterpret_cast<uint64_t *>(db + o_Y) + (size_t)b * b * li;
+        di.H = reinterpret_cast<uint64_t *>(db + o_H) + (size_t)F.fin.count * b * li;
+        std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
+        std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
+        std::memcpy(hb + o_coef + 8 * (size_t)b * chain_at, it.coef.data(), 8 * it.coef.size());
+        std::memcpy(hb + o_cu + 2 * (size_t)F.nv * chain_at, it.chain_u.data(), 2 * it.chain_u.size());
+        std::memcpy(hb + o_cg + 4 * chain_at, it.chain_g.data(), 4 * it.chain_g.size());
+        std::memcpy(hb + o_cp + 4 * chain_at, it.chain_pole.data(), 4 * it.chain_pole.size());
+        item_chain0[li] = chain_at;
+        chain_at += it.nchain();
+    }
+    DevTile *htiles = reinterpret_cast<DevTile *>(hb + o_tiles);
+    for (size_t k = 0; k < tiles.size(); k++) {
+        htiles[k] = tiles[k];
+        htiles[k].chain0 += (int32_t)item_chain0[tiles[k].item];
+    }
+    std::memset(hb + o_err, 0, 4);
+
+    auto t1 = std::chrono::steady_clock::now();
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    hipError_t he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, stream);
+    (void)hipEventRecord(e0, stream);
+    if (he == hipSuccess)
+        he = launch_reduce(df, reinterpret_cast<const DevItem *>(db + o_items),
+                           reinterpret_cast<const DevTile *>(db + o_tiles), (int)tiles.size(),
+                           reinterpret_cast<const int16_t *>(db + o_cu), reinterpret_cast<const int32_t *>(db + o_cg),
+                           reinterpret_cast<const int32_t *>(db + o_cp),
+                           reinterpret_cast<uint64_t *>(db + o_hbuf), ct,
+                           reinterpret_cast<int *>(db + o_err), stream);
+    if (he == hipSuccess)
+        he = launch_assemble(df, reinterpret_cast<const DevItem *>(db + o_items), nlive,
+                             reinterpret_cast<const uint64_t *>(db + o_hbuf), stream);
+    (void)hipEventRecord(e1, stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(hb + o_Y, db + o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(hb + o_err, db + o_err, 4, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    float dev_ms = 0;
+    if (he == hipSuccess) (void)hipEventElapsedTime(&dev_ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(CR_EDEVICE, std::string("HIP error: ") + hipGetErrorString(he));
+    int derr;
+    std::memcpy(&derr, hb + o_err, 4);
+    if (derr) return fail(CR_ESELFCHECK, "device reduction invariant violated (code " + std::to_string(derr) + ")");
+    (void)t1;
+
+    // ---- finish: unscale, Q(T)
+    auto t2 = std::chrono::steady_clock::now();
+    const uint64_t *Yh = reinterpret_cast<const uint64_t *>(hb + o_Y);
+    parallel_for(nlive, [&](int li) {
+        const int i = live[li];
+        const size_t bb = (size_t)b * b;
+        st[i] = finish_item(F, items[i], Yh + bb * li, frob + bb * i, col_pole + (size_t)b * i,
+                            col_prec + (size_t)b * i, lpoly + (size_t)4 * (b + 1) * i, errs[i]);
+        if (frob_scaled) std::memcpy(frob_scaled + bb * i, Yh + bb * li, 8 * bb);
+    });
+    const double finish_ms = ms_since(t2);
+    cr_status first = CR_OK;
+    for (int i = 0; i < count; i++) {
+        if (item_status) item_status[i] = st[i];
+        if (st[i] != CR_OK && first == CR_OK) {
+            first = st[i];
+            g_err = "item " + std::to_string(i) + ": " + errs[i];
+        }
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        for (int i : live) {
+            stats->start_blocks += items[i].nchain();
+            stats->column_steps += items[i].column_steps;
+            stats->chunks += items[i].chunks;
+        }
+        stats->setup_ms = setup_ms;
+        stats->device_ms = dev_ms;
+        stats->finish_ms = finish_ms;
+    }
+    return first;
+}
+
+}  // extern "C"

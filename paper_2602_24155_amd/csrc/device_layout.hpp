@@ -1,0 +1,48 @@
+// Device-side data layout shared by the C-ABI host code and the HIP kernels.
+#pragma once
+#include <cstdint>
+
+namespace crf {
+
+// Per-family index tables (depend on nvars, degree and S only).
+struct DevFamily {
+    int nv, n, d;
+    uint32_t smask;
+    int s;      // dim Homog_{dn-n}: length of the reduced vectors g
+    int T;      // dim Homog_D: target of J_S
+    int nsrc;   // sum of the J_S source blocks
+    int F;      // dim Homog_{dn-n-1}: pole-n numerators
+    int ndir;   // directions v with |v| = d
+    int nfinU;  // final exponents U with |U| = |S| - 1
+    const int16_t *colmap;  // ndir x s : tgt index of v + g_k - 1_S (or -1)
+    const int16_t *gsrc;    // s x nv   : src index of r - 1_S + [i in S] e_i (or -1)
+    const int16_t *gw;      // s x nv   : r_i + [i not in S]
+    const int16_t *finmap;  // nfinU x s: fin index of U + g_k - 1_S (or -1)
+    const int8_t *dirs;     // ndir x nv
+    const int8_t *finU;     // nfinU x nv
+};
+
+// Per-hypersurface data.
+struct DevItem {
+    uint64_t q;      // p^M
+    uint64_t mu;     // Barrett constant floor(2^(2 sbits + 8) / q)
+    int32_t sbits;   // bit length of q (<= 55)
+    int32_t b;       // side of Phi'
+    int32_t chain0;  // first chain (global index)
+    int32_t nchain;
+    const uint64_t *psi;   // nsrc x T right inverse of J_S
+    const uint64_t *rho;   // b x F Griffiths-Dwork coordinate map
+    const uint64_t *coef;  // nchain x b start coefficients
+    uint64_t *Y;           // b x b output (coordinates, mod q)
+    uint64_t *H;           // F x b scratch: summed pole-n numerators
+};
+
+// A tile of chains of one item processed by one workgroup.
+struct DevTile {
+    int32_t item;
+    int32_t chain0;  // global index of the first chain
+    int32_t count;
+    int32_t steps;   // longest chain of the tile (pole - n)
+};
+
+}  // namespace crf

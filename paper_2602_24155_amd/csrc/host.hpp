@@ -1,0 +1,124 @@
+// Host-side setup and finishing of the controlled-reduction pipeline.
+//
+// Everything here runs once per hypersurface (setup) or once per family
+// (index tables); the per-step work runs in the HIP kernels of kernels.hip.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/crfrob.h"
+
+namespace crf {
+
+using u64 = uint64_t;
+using u128 = unsigned __int128;
+using i128 = __int128;
+
+constexpr int kMaxVars = 6;
+
+// ---------------------------------------------------------------- modulus
+// Residues mod q = p^M, q < 2^55.  Barrett reduction of x < 2^(2*sbits+8):
+//   qhat = ((x >> (sbits-1)) * mu) >> (sbits+9),  mu = floor(2^(2*sbits+8) / q),
+// then at most two corrective subtractions.  The device uses the same formula
+// with the constants computed here.
+struct ModQ {
+    u64 q = 0;
+    int sbits = 0;
+    u64 mu = 0;
+    void init(u64 modulus);
+    u64 reduce(u128 x) const {
+        if (sbits > 55) return (u64)(x % q);  // only the small finishing moduli exceed the Barrett range
+        u64 x1 = (u64)(x >> (sbits - 1));
+        u64 qh = (u64)(((u128)x1 * mu) >> (sbits + 9));
+        u64 r = (u64)x - qh * q;
+        while (r >= q) r -= q;
+        return r;
+    }
+    u64 mul(u64 a, u64 b) const { return reduce((u128)a * b); }
+    u64 add(u64 a, u64 b) const { u64 s = a + b; return s >= q ? s - q : s; }
+    u64 sub(u64 a, u64 b) const { return a >= b ? a - b : a + q - b; }
+    u64 inv(u64 a) const;  // a must be a unit
+    u64 from_int(long long v) const {
+        long long r = v % (long long)q;
+        return (u64)(r < 0 ? r + (long long)q : r);
+    }
+};
+
+// ---------------------------------------------------------------- monomials
+// Homogeneous monomials of one degree in nv variables, lex-descending.
+// rank() maps an exponent vector to its position by counting the monomials
+// that precede it (combinatorial number system).
+struct MonoSpace {
+    int nv = 0, deg = -1, count = 0;
+    std::vector<int8_t> exps;  // count x nv
+    void init(int nvars, int degree);
+    int rank(const int *e) const;  // -1 if e has a negative entry or wrong degree
+    const int8_t *at(int k) const { return exps.data() + (size_t)k * nv; }
+};
+
+long long binom(int n, int k);
+long long count_monomials(int nv, int deg);
+
+// ---------------------------------------------------------------- family
+// Index tables that depend only on (nvars, degree, S).
+struct Family {
+    int nv = 0, n = 0, d = 0, nS = 0;
+    uint32_t smask = 0;  // bit i set <=> i in S
+    int D = 0;           // degree of the J_S target: dn + d - n - |S|
+    MonoSpace coeff;     // Homog_d          (input coefficients)
+    MonoSpace g;         // Homog_{dn-n}     (s: numerators g of Proposition 3.3)
+    MonoSpace tgt;       // Homog_D          (x^v g / x^S)
+    MonoSpace fin;       // Homog_{dn-n-1}   (pole-n numerators)
+    MonoSpace dirs;      // Homog_d          (directions v, |v| = d)
+    std::vector<MonoSpace> srcblk;  // block i: Homog_{D-d+1} (i in S) or Homog_{D-d}
+    std::vector<int> srcoff;        // offsets of the blocks, size nv+1
+    int nsrc = 0;
+    // colmap[dir*s + k] = tgt rank of v_dir + g_k - 1_S, or -1
+    std::vector<int16_t> colmap;
+    // gather for R_{u,v}: for output monomial r (g-space) and variable i,
+    // gsrc = src index of r - 1_S + [i in S] e_i (or -1), gw = r_i + [i not in S]
+    std::vector<int16_t> gsrc, gw;
+    // final exponents U (|U| = |S| - 1) and finmap[Uidx*s + k] = fin rank of U + g_k - 1_S or -1
+    MonoSpace finU;
+    std::vector<int16_t> finmap;
+    bool init(int nvars, int degree, uint32_t s_mask, std::string &err);
+};
+
+// ---------------------------------------------------------------- per item
+struct ItemSetup {
+    int p = 0, r = 0, N = 0, M = 0, b = 0;
+    ModQ mq;
+    std::vector<int> hodge;          // |B_m|, m = 1..n (index m-1)
+    std::vector<int> col_pole;       // b
+    std::vector<u64> psi;            // nsrc x T, right inverse of J_S mod q
+    std::vector<u64> rho;            // b x F, Griffiths-Dwork coordinates of pole-n numerators
+    // start blocks (one chain each), sorted by pole descending
+    std::vector<int16_t> chain_u;    // nchain x nv
+    std::vector<int32_t> chain_g;    // g-space rank of the Tweak remainder
+    std::vector<int32_t> chain_pole; // pole order P
+    std::vector<u64> coef;           // nchain x b
+    std::vector<int> col_shift;      // v_p((p s_m - 1)!) - (m - 1)
+    std::vector<int> col_prec;       // M - col_shift
+    std::vector<u64> col_unit;       // unit part of (p s_m - 1)!/(n-1)! mod q
+    int64_t column_steps = 0, chunks = 0;
+    int nchain() const { return (int)chain_g.size(); }
+};
+
+// Precision of Section 2.5 under the reading in crfrob.h.
+bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_override, int n_override,
+                      int &r, int &N, int &M, std::string &err);
+
+// S-smoothness test + full setup of one item.  Returns CR_OK or an error status.
+cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_override,
+                     int n_override, ItemSetup &out, std::string &err, bool smooth_only = false);
+
+// Unscale the device result Y (b x b mod q) and recover Q(T).
+cr_status finish_item(const Family &fam, const ItemSetup &it, const u64 *Y, u64 *frob,
+                      int32_t *col_pole, int32_t *col_prec, int64_t *lpoly, std::string &err);
+
+// Depth-first chunk schedule statistics of one chain (host mirror of the device
+// policy, used for counters only).
+void count_chunks(const Family &fam, const int16_t *u0, int pole, int64_t &chunks);
+
+}  // namespace crf

@@ -1,0 +1,87 @@
+"""Host-only checks of the C-ABI library (no device needed).
+
+* libcrfrob.so loads and exports every function declared in include/crfrob.h;
+* the pure host entry points agree with the oracle: monomial order,
+  dimensions, precision rule, smoothness decisions on a candidate stream.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.cohomology import is_s_smooth
+from oracle.poly import from_coeffs, monomials
+from oracle.precision import precision_parameters
+from paper_2602_24155_amd import crfrob as C
+from paper_2602_24155_amd import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "crfrob.h")).read()
+    declared = set(re.findall(r"^\s*(?:cr_status|const char \*|void)\s*\*?\s*(cr_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    L = C.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(C.EXPORTS)
+
+
+@pytest.mark.parametrize("nv,d", [(3, 4), (3, 5), (4, 4), (4, 5), (6, 3), (5, 3)])
+def test_monomials_and_dims(nv, d):
+    mons = C.cr_monomials(nv, d)
+    assert [tuple(int(x) for x in m) for m in mons] == monomials(nv, d)
+    nco, s, b = C.cr_query_dims(nv, d)
+    n = nv - 1
+    assert s == len(monomials(nv, d * n - n))
+    assert b == ((d - 1) ** nv + (-1) ** nv * (d - 1)) // d
+
+
+@pytest.mark.parametrize("nv,d,p", [(3, 4, 7), (3, 5, 11), (3, 5, 31), (3, 5, 47), (4, 4, 7), (4, 4, 13),
+                                    (5, 3, 11), (6, 3, 7)])
+def test_precision_matches_oracle(nv, d, p):
+    n = nv - 1
+    hodge = {}
+    for m in range(1, n + 1):
+        k = d * m - n - 1
+        hodge[m] = sum((-1) ** j * __import__("math").comb(nv, j) *
+                       __import__("math").comb(k - j * (d - 1) + n, n)
+                       for j in range(nv) if k - j * (d - 1) >= 0)
+    r, Nm, _s, M = precision_parameters(p, n, hodge)
+    assert C.cr_precision(C.family(nv, d), p) == (r, r + 1, M)
+
+
+@pytest.mark.parametrize("name", ["quartic_curve_f7", "quintic_curves_mixed", "quartic_k3_mixed"])
+def test_smoothness_agrees_with_oracle(name):
+    w = workload.WORKLOADS[name]
+    fam = C.family(w.nvars, w.degree)
+    for j in range(3):
+        p, gen = workload.stream(name, j)
+        for _ in range(4):
+            c = next(gen)
+            f = {e: v % p for e, v in from_coeffs(w.nvars, w.degree, c).items() if v % p}
+            assert C.cr_check_smooth(fam, p, c) == is_s_smooth(f, w.nvars, w.degree, p, list(range(w.nvars)))
+    # a visibly singular form: x0^d
+    c = [1] + [0] * (w.ncoeff - 1)
+    assert not C.cr_check_smooth(fam, 7 if 7 in w.primes else w.primes[0], c)
+
+
+def test_invalid_arguments_are_rejected():
+    fam = C.family(3, 5)
+    with pytest.raises(C.CrError) as e:
+        C.cr_frobenius_batch(fam, [31], [[40] * 21])
+    assert e.value.status == C.CR_EINVAL
+    with pytest.raises(C.CrError) as e:
+        C.cr_precision(C.family(2, 5), 31)
+    assert e.value.status == C.CR_EINVAL
+
+
+def test_bad_prime_statuses_without_device():
+    fam = C.family(3, 5)
+    # p = 9 is not prime, p = 53 is out of range: rejected by host validation
+    with pytest.raises(C.CrError):
+        C.cr_check_smooth(fam, 9, [1] * 21)
+    with pytest.raises(C.CrError):
+        C.cr_check_smooth(fam, 53, [1] * 21)

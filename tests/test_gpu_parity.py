@@ -1,0 +1,87 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bar: bit-exact.  Every comparison is on integers: the scaled Frobenius
+coordinates mod p^M, Phi' mod p^(column precision), column poles/precisions
+and the integer L-polynomial.
+"""
+import numpy as np
+import pytest
+
+from oracle.diagonal import fermat_coeffs
+from oracle.frobenius import frobenius
+from oracle.lpoly import weil_root_check
+from oracle.pointcount import count_projective
+from oracle.poly import from_coeffs
+from paper_2602_24155_amd import crfrob as C
+from tests.gpu_common import assert_item_matches_oracle, run_batch, workload_items
+
+pytestmark = pytest.mark.gpu
+
+
+def test_quartic_curve_f7():
+    items = workload_items("quartic_curve_f7", [0])
+    res = run_batch(3, 4, items)
+    assert_item_matches_oracle(res, 0, 3, 4, *items[0])
+
+
+def test_quintic_curves_mixed_primes():
+    items = workload_items("quintic_curves_mixed", range(6))
+    res = run_batch(3, 5, items)
+    for i, (p, c) in enumerate(items):
+        assert_item_matches_oracle(res, i, 3, 5, p, c)
+
+
+def test_quintic_curves_p31():
+    items = workload_items("quintic_curves_p31", range(3))
+    res = run_batch(3, 5, items)
+    for i, (p, c) in enumerate(items):
+        assert_item_matches_oracle(res, i, 3, 5, p, c)
+
+
+@pytest.mark.parametrize("nv,d,p", [(3, 4, 7), (3, 4, 13), (3, 5, 11), (3, 5, 19), (3, 5, 41), (4, 4, 7),
+                                    (4, 4, 13)])
+def test_fermat(nv, d, p):
+    c = fermat_coeffs(nv, d)
+    res = run_batch(nv, d, [(p, c)])
+    assert_item_matches_oracle(res, 0, nv, d, p, c)
+
+
+def test_ragged_batch_and_bad_items():
+    """Mixed batch: valid items of several primes around singular / invalid ones."""
+    good = workload_items("quintic_curves_mixed", range(6, 9))
+    items = [good[0], (31, [0] * 21), good[1], (11, [1] + [0] * 20), good[2]]
+    fam = C.family(3, 5)
+    res = C.cr_frobenius_batch(fam, [p for p, _ in items], [c for _, c in items], raise_on_error=False)
+    assert res["status"] == C.CR_ESINGULAR
+    assert list(res["item_status"]) == [0, C.CR_ESINGULAR, 0, C.CR_ESINGULAR, 0]
+    for i in (0, 2, 4):
+        assert_item_matches_oracle(res, i, 3, 5, *items[i])
+
+
+def test_repeated_calls_identical():
+    items = workload_items("quintic_curves_mixed", range(9, 11))
+    a = run_batch(3, 5, items)
+    b = run_batch(3, 5, items)
+    assert np.array_equal(a["scaled"], b["scaled"]) and a["lpoly"] == b["lpoly"]
+
+
+def test_empty_batch():
+    res = C.cr_frobenius_batch(C.family(3, 5), [], np.zeros((0, 21), dtype=np.uint32))
+    assert res["status"] == C.CR_OK
+
+
+def test_full_size_headline_batch():
+    """256 random quintic curves at p = 31 in one call (the benchmark launch):
+    every item satisfies the Weil bound and the brute-force count #C(F_31);
+    sampled items are compared with the oracle bit for bit."""
+    items = workload_items("quintic_curves_p31", range(256))
+    res = run_batch(3, 5, items)
+    assert res["status"] == C.CR_OK
+    for i, (p, c) in enumerate(items):
+        a = res["lpoly"][i]
+        assert len(a) == 13 and a[0] == 1 and a[12] == p ** 6
+        assert weil_root_check(a, p, 1)
+        if i % 16 == 0:
+            assert count_projective(from_coeffs(3, 5, c), 3, p, 1) == p + 1 + a[1]
+    for i in (0, 100, 255):
+        assert_item_matches_oracle(res, i, 3, 5, *items[i])
