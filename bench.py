@@ -1,0 +1,146 @@
+"""Benchmark: Frobenius matrices per second for a batch of random smooth plane
+quintic curves over F_31 (256 curves per step), plus modular mat-vecs/s.
+
+One step = one cr_frobenius_batch call over the whole batch: host setup,
+device reduction of every start term to pole n, device Griffiths-Dwork
+assembly, host unscaling and integer L-polynomials.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  `roofline` describes the chain-reduction kernel (the
+dominant one), timed with HIP events on the stream it runs on; `cpu_baseline`
+times the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
+
+
+def limbs_for(q):
+    """Balanced base-256 digits needed for residues mod q."""
+    L = 1
+    while 256 ** L <= q:
+        L += 1
+    return L
+
+
+def _oracle_one(args):
+    nv, d, p, c = args
+    from oracle.frobenius import frobenius
+    frobenius(nv, d, p, c)
+    return 1
+
+
+def cpu_baseline(name, items, budget_s=20.0):
+    """The CPU oracle timed on the first items of the workload, on a pool of
+    host processes (one hypersurface per task) until ~budget_s of CPU work."""
+    import multiprocessing as mp
+    from paper_2602_24155_amd import workload
+    w = workload.WORKLOADS[name]
+    cores = max(1, min(8, os.cpu_count() or 1))
+    # calibrate on one item in this process
+    t = time.perf_counter()
+    _oracle_one((w.nvars, w.degree, items[0][0], items[0][1]))
+    per = time.perf_counter() - t
+    n = max(cores, min(len(items), int(budget_s / max(per, 1e-3))))
+    n = min(n, len(items))
+    sample = [(w.nvars, w.degree, p, c) for p, c in items[:n]]
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        done = sum(pool.map(_oracle_one, sample, chunksize=1))
+    wall = time.perf_counter() - t
+    return {"value": done / wall, "unit": "frobenius_matrices/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of the %d %s hypersurfaces, one per task on %d processes "
+                      "(exact-integer Python + plain-C oracle, %.1f s wall)" % (n, len(items), name, cores, wall)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="quintic_curves_p31")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the hypersurfaces of a batch are independent; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2602_24155_amd import crfrob as C
+    from paper_2602_24155_amd import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    w = workload.WORKLOADS[args.workload]
+    fam = C.family(w.nvars, w.degree, w.s_mask)
+    items = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(fam, p, c)) for j in range(w.count)]
+    primes = [p for p, _ in items]
+    coeffs = [c for _, c in items]
+
+    for _ in range(args.warmup):
+        C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
+    torch.cuda.synchronize()
+    tot = {"reduce_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
+        for k in tot:
+            tot[k] += getattr(res["stats"], k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = res["stats"]
+    wall = t1 - t0
+    value = len(items) * args.steps / wall
+    _nco, s, b = C.cr_query_dims(w.nvars, w.degree)
+    # algorithmic work of one step: column_steps products s x s . s mod p^M,
+    # priced as int8 MFMA ops with L balanced base-256 digits per residue
+    work = 0
+    for p in sorted(set(primes)):
+        _r, _N, M = C.cr_precision(fam, p)
+        L = limbs_for(p ** M)
+        work_p = 2 * s * s * L * L
+        work += work_p * sum(1 for q in primes if q == p)
+    work_per_colstep = work / len(primes)
+    red_s = tot["reduce_ms"] / 1e3 / args.steps
+    achieved = st.column_steps * work_per_colstep / red_s / 1e12
+    line = {
+        "metric": "Frobenius matrices/sec (batched quintic curves, p=31) + modular matvecs/sec vs plain",
+        "value": value,
+        "unit": "frobenius_matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 residues mod p^M (int8-limb / int32 exact products)",
+        "data": "synthetic: seeded random dense smooth curves, coefficients uniform in F_p",
+        "config": {"workload": args.workload, "count": len(items), "nvars": w.nvars, "degree": w.degree,
+                   "primes": sorted(set(primes)), "policy": "depth-first",
+                   "start_blocks": st.start_blocks, "column_steps_per_step": st.column_steps},
+        "matvecs_per_s": st.column_steps / red_s,
+        "breakdown_ms": {k: v / args.steps for k, v in tot.items()},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_reduce_chains",
+                     "work_per_column_step_int8_ops": work_per_colstep},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, items)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,8 @@ typedef struct {
     int32_t policy;   /* cr_policy */
     int32_t r;        /* relative precision override; 0 = derive (header comment) */
     int32_t n_series; /* series order override N_m for every m; 0 = r + 1 */
+    int32_t engine;   /* reduction kernel: 0 = auto (int8-digit MFMA kernel when the family's
+                         tables fit it, else the 64-bit VALU kernel), 1 = 64-bit VALU kernel */
 } cr_family;
 
 /* Per-call statistics (all counts are summed over the batch). */
@@ -81,7 +83,11 @@ typedef struct {
     int64_t chunks;        /* reduction chunks (u, v, k) */
     double setup_ms;       /* host setup wall time */
     double device_ms;      /* device time of the reduction and assembly kernels */
+    double reduce_ms;      /* device time of the chain-reduction kernel alone (HIP events) */
+    double assemble_ms;    /* device time of the Griffiths-Dwork assembly kernel alone */
     double finish_ms;      /* host unscaling and L-polynomial recovery */
+    int32_t engine;        /* kernel that ran: 0 = int8-digit MFMA, 1 = 64-bit VALU */
+    int32_t pad_;
 } cr_stats;
 
 /* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},

@@ -22,13 +22,16 @@ EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
 
 class cr_family(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
-                ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32)]
+                ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32),
+                ("engine", ctypes.c_int32)]
 
 
 class cr_stats(ctypes.Structure):
     _fields_ = [("start_blocks", ctypes.c_int64), ("column_steps", ctypes.c_int64),
                 ("chunks", ctypes.c_int64), ("setup_ms", ctypes.c_double),
-                ("device_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
+                ("assemble_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
+                ("engine", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class CrError(RuntimeError):
@@ -72,8 +75,11 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0):
-    return cr_family(nvars, degree, s_mask, policy, r, n_series)
+ENGINE_AUTO, ENGINE_VALU = 0, 1
+
+
+def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO):
+    return cr_family(nvars, degree, s_mask, policy, r, n_series, engine)
 
 
 def cr_query_dims(nvars, degree):

@@ -23,6 +23,11 @@ hipError_t launch_reduce(const DevFamily &fam, const DevItem *items, const DevTi
                          int *err, hipStream_t stream);
 hipError_t launch_assemble(const DevFamily &fam, const DevItem *items, int nitems, const uint64_t *hbuf,
                            hipStream_t stream);
+bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb);
+hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int *err,
+                              int D, hipStream_t stream);
+bool mfma_supports_digits(int D);
 }  // namespace crf
 
 using namespace crf;
@@ -242,14 +247,40 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     auto t0 = std::chrono::steady_clock::now();
 
     // ---- host setup, one item per task
+    DevFamily df{};
+    df.nv = F.nv;
+    df.n = F.n;
+    df.d = F.d;
+    df.smask = F.smask;
+    df.s = F.g.count;
+    df.T = F.tgt.count;
+    df.nsrc = F.nsrc;
+    df.F = F.fin.count;
+    df.ndir = F.dirs.count;
+    df.nfinU = F.finU.count;
+    int nrt = 0, nkb = 0;
+    const bool want_mfma = fam->engine == 0 && mfma_shape(df, nrt, nkb);
     std::vector<ItemSetup> items(count);
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
+    std::vector<DigitParams> dps(count);
+    std::vector<char> digit_ok(count, 0);
     parallel_for(count, [&](int i) {
         st[i] = setup_item(F, primes[i], coeffs + (size_t)i * nco, fam->r, fam->n_series, items[i], errs[i]);
         if (st[i] == CR_OK && items[i].b != b) {
             st[i] = CR_ESELFCHECK;
             errs[i] = "basis size differs from the Hodge numbers";
+        }
+        if (st[i] == CR_OK && want_mfma) {
+            ItemSetup &it = items[i];
+            int umax = 0;
+            for (size_t k = 0; k < it.chain_u.size(); k++) umax = std::max<int>(umax, it.chain_u[k]);
+            const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
+            if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, dps[i]) && mfma_supports_digits(dps[i].D)) {
+                it.apack.resize((size_t)nrt * dps[i].D * nkb * 1024);
+                pack_psi_digits(F, it, dps[i], nrt, nkb, it.apack.data());
+                digit_ok[i] = 1;
+            }
         }
     });
     const double setup_ms = ms_since(t0);
@@ -276,32 +307,39 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     }
     size_t nchain = 0, psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
     for (int i : live) nchain += items[i].nchain();
-    // choose chains per workgroup so the LDS tile stays within 64 KiB
-    DevFamily df{};
-    df.nv = F.nv;
-    df.n = F.n;
-    df.d = F.d;
-    df.smask = F.smask;
-    df.s = F.g.count;
-    df.T = F.tgt.count;
-    df.nsrc = F.nsrc;
-    df.F = F.fin.count;
-    df.ndir = F.dirs.count;
-    df.nfinU = F.finU.count;
+    bool use_mfma = want_mfma;
+    for (int li = 0; li < nlive && use_mfma; li++) use_mfma = digit_ok[live[li]] != 0;
     int ct = 32;
-    while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
-    if (reduce_lds_bytes(df, ct) > 64 * 1024) return fail(CR_EINVAL, "family too large for the LDS tile");
+    if (!use_mfma) {
+        while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
+        if (reduce_lds_bytes(df, ct) > 64 * 1024) return fail(CR_EINVAL, "family too large for the LDS tile");
+    }
+    // tiles of ct chains of one item; for the MFMA kernel grouped by digit count D
     std::vector<DevTile> tiles;
-    for (int li = 0; li < nlive; li++) {
-        const ItemSetup &it = items[live[li]];
-        for (int c0 = 0; c0 < it.nchain(); c0 += ct) {
-            DevTile t{};
-            t.item = li;
-            t.count = std::min(ct, it.nchain() - c0);
-            t.chain0 = c0;  // item-relative for now
-            t.steps = it.chain_pole[c0] - F.n;
-            tiles.push_back(t);
+    std::vector<std::pair<int, std::pair<int, int>>> groups;  // (D, (first tile, count))
+    std::vector<int> dvals;
+    if (use_mfma) {
+        for (int li = 0; li < nlive; li++) dvals.push_back(dps[live[li]].D);
+        std::sort(dvals.begin(), dvals.end());
+        dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
+    } else {
+        dvals.push_back(0);
+    }
+    for (int D : dvals) {
+        const int first = (int)tiles.size();
+        for (int li = 0; li < nlive; li++) {
+            if (use_mfma && dps[live[li]].D != D) continue;
+            const ItemSetup &it = items[live[li]];
+            for (int c0 = 0; c0 < it.nchain(); c0 += ct) {
+                DevTile t{};
+                t.item = li;
+                t.count = std::min(ct, it.nchain() - c0);
+                t.chain0 = c0;  // item-relative for now
+                t.steps = it.chain_pole[c0] - F.n;
+                tiles.push_back(t);
+            }
         }
+        groups.push_back({D, {first, (int)tiles.size() - first}});
     }
     // device layout
     size_t off = 0;
@@ -313,7 +351,13 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     const size_t o_tables = take(fe->tables.size());
     const size_t o_items = take(sizeof(DevItem) * std::max(nlive, 1));
     const size_t o_tiles = take(sizeof(DevTile) * std::max<size_t>(tiles.size(), 1));
-    const size_t o_psi = take(8 * psi_len * nlive);
+    const size_t o_psi = take(use_mfma ? 0 : 8 * psi_len * nlive);
+    std::vector<size_t> apack_off(nlive, 0);
+    size_t o_ditems = 0;
+    if (use_mfma) {
+        o_ditems = take(sizeof(DevDigitItem) * nlive);
+        for (int li = 0; li < nlive; li++) apack_off[li] = take(items[live[li]].apack.size());
+    }
     const size_t o_rho = take(8 * rho_len * nlive);
     const size_t o_coef = take(8 * (size_t)b * nchain);
     const size_t o_cu = take(2 * (size_t)F.nv * nchain);
@@ -352,7 +396,35 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + (size_t)b * chain_at;
         di.Y = reinterpret_cast<uint64_t *>(db + o_Y) + (size_t)b * b * li;
         di.H = reinterpret_cast<uint64_t *>(db + o_H) + (size_t)F.fin.count * b * li;
-        std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
+        if (use_mfma) {
+            const DigitParams &dp = dps[live[li]];
+            DevDigitItem &dd = reinterpret_cast<DevDigitItem *>(hb + o_ditems)[li];
+            dd.Bd = dp.Bd;
+            dd.Qd = dp.Qd;
+            dd.invQ = dp.invQ;
+            dd.BHd = dp.BHd;
+            dd.invBH = dp.invBH;
+            dd.Bh = dp.Bh;
+            dd.Bsplit = dp.Bsplit;
+            dd.invBsplit = dp.invBsplit;
+            dd.bias = dp.bias;
+            dd.Qp = dp.Qp;
+            dd.q = it.mq.q;
+            dd.magic = dp.magic;
+            dd.shift = dp.shift;
+            dd.B = dp.B;
+            dd.halfB = dp.halfB;
+            dd.D = dp.D;
+            dd.h = dp.h;
+            dd.ds = dp.ds;
+            dd.z32 = dp.z32;
+            dd.chain0 = (int32_t)chain_at;
+            dd.nchain = it.nchain();
+            dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
+            std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
+        } else {
+            std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
+        }
         std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
         std::memcpy(hb + o_coef + 8 * (size_t)b * chain_at, it.coef.data(), 8 * it.coef.size());
         std::memcpy(hb + o_cu + 2 * (size_t)F.nv * chain_at, it.chain_u.data(), 2 * it.chain_u.size());
@@ -369,18 +441,32 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     std::memset(hb + o_err, 0, 4);
 
     auto t1 = std::chrono::steady_clock::now();
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, em;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
+    (void)hipEventCreate(&em);
     hipError_t he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, stream);
     (void)hipEventRecord(e0, stream);
-    if (he == hipSuccess)
+    if (he == hipSuccess && use_mfma) {
+        for (auto &g : groups) {
+            if (he != hipSuccess) break;
+            he = launch_reduce_mfma(df, reinterpret_cast<const DevDigitItem *>(db + o_ditems),
+                                    reinterpret_cast<const DevTile *>(db + o_tiles) + g.second.first, g.second.second,
+                                    reinterpret_cast<const int16_t *>(db + o_cu),
+                                    reinterpret_cast<const int32_t *>(db + o_cg),
+                                    reinterpret_cast<const int32_t *>(db + o_cp),
+                                    reinterpret_cast<uint64_t *>(db + o_hbuf), reinterpret_cast<int *>(db + o_err),
+                                    g.first, stream);
+        }
+    }
+    else if (he == hipSuccess)
         he = launch_reduce(df, reinterpret_cast<const DevItem *>(db + o_items),
                            reinterpret_cast<const DevTile *>(db + o_tiles), (int)tiles.size(),
                            reinterpret_cast<const int16_t *>(db + o_cu), reinterpret_cast<const int32_t *>(db + o_cg),
                            reinterpret_cast<const int32_t *>(db + o_cp),
                            reinterpret_cast<uint64_t *>(db + o_hbuf), ct,
                            reinterpret_cast<int *>(db + o_err), stream);
+    (void)hipEventRecord(em, stream);
     if (he == hipSuccess)
         he = launch_assemble(df, reinterpret_cast<const DevItem *>(db + o_items), nlive,
                              reinterpret_cast<const uint64_t *>(db + o_hbuf), stream);
@@ -388,10 +474,15 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     if (he == hipSuccess) he = hipMemcpyAsync(hb + o_Y, db + o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipMemcpyAsync(hb + o_err, db + o_err, 4, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
-    float dev_ms = 0;
-    if (he == hipSuccess) (void)hipEventElapsedTime(&dev_ms, e0, e1);
+    float dev_ms = 0, red_ms = 0, asm_ms = 0;
+    if (he == hipSuccess) {
+        (void)hipEventElapsedTime(&dev_ms, e0, e1);
+        (void)hipEventElapsedTime(&red_ms, e0, em);
+        (void)hipEventElapsedTime(&asm_ms, em, e1);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(em);
     if (he != hipSuccess) return fail(CR_EDEVICE, std::string("HIP error: ") + hipGetErrorString(he));
     int derr;
     std::memcpy(&derr, hb + o_err, 4);
@@ -426,6 +517,9 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         }
         stats->setup_ms = setup_ms;
         stats->device_ms = dev_ms;
+        stats->reduce_ms = red_ms;
+        stats->engine = use_mfma ? 0 : 1;
+        stats->assemble_ms = asm_ms;
         stats->finish_ms = finish_ms;
     }
     return first;

@@ -46,3 +46,32 @@ struct DevTile {
 };
 
 }  // namespace crf
+
+namespace crf {
+
+// Digit (p-adic) representation used by the MFMA reduction kernel.  Residues
+// live in Z/Q', Q' = B^D with B = p^e <= 169 (a multiple-power of p at least
+// p^M), as D balanced base-B digits (|digit| <= (B-1)/2, stored as int8).
+// Products of digits at positions >= D are multiples of Q' and are dropped.
+struct DevDigitItem {
+    double Bd;            // base B
+    double Qd, invQ;      // Q' = B^D
+    double BHd, invBH;    // B^(D-h)
+    double Bh;            // B^h
+    double Bsplit, invBsplit;  // B^ds: the digit split cuts x into x_hi * B^ds + x_lo
+    double bias;          // sum_j halfB B^j when digits are balanced, else 0
+    uint64_t Qp;          // Q'
+    uint64_t q;           // p^M (final reduction)
+    uint32_t magic;       // floor division by B of a value < 2^24: (v * magic) >> (32 + shift)
+    int32_t shift;
+    int32_t B;
+    int32_t halfB;        // subtracted from every digit when balanced, else 0
+    int32_t D;            // digits
+    int32_t h;            // Horner split position
+    int32_t ds;           // digit split position
+    int32_t z32;          // 1: the weighted digit sums fit int32
+    int32_t chain0, nchain;
+    const int8_t *apack;  // NRT x D x NKB x 64 lanes x 16 bytes: psi digits in MFMA A-fragment order
+};
+
+}  // namespace crf

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstring>
 #include <unordered_map>
 
@@ -700,6 +701,99 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         out.col_unit.push_back(unit);
     }
     return CR_OK;
+}
+
+// ------------------------------------------------------------------ digit representation
+bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams &dp) {
+    int e = 1;
+    while ((long long)std::llround(std::pow((double)p, e + 1)) <= 169) e++;
+    const long long B = (long long)std::llround(std::pow((double)p, e));
+    const int D = (M + e - 1) / e;
+    if (D > dmax) return false;
+    long double Q = 1;
+    for (int k = 0; k < D; k++) Q *= B;
+    if (Q >= std::ldexp(1.0L, 52)) return false;
+    const long long half = (B - 1) / 2;
+    // |S_k| <= D T half^2 (balanced digits on both sides), |Z_k| <= nv wtmax |S_k|
+    const long double Smax = (long double)D * T * half * half;
+    const long double Zmax = (long double)nv * (long double)wtmax * Smax;
+    const long double lim = std::ldexp(1.0L, 53);
+    auto span = [&](int a, int b) {  // Zmax * sum_{k=a}^{b-1} B^(k-a)
+        long double acc = 0, pw = 1;
+        for (int k = a; k < b; k++) {
+            acc += pw;
+            pw *= B;
+        }
+        return Zmax * acc;
+    };
+    int h = -1;
+    for (int cand = 1; cand <= D; cand++)
+        if (span(cand, D) < lim && span(0, cand) < lim) {
+            h = cand;
+            break;
+        }
+    if (h < 0) return false;
+    // digit split: x in [0, Q') as x_hi B^ds + x_lo with both parts below 2^24
+    const int ds = (D + 1) / 2;
+    long double Bds = 1, Brest = 1;
+    for (int k = 0; k < ds; k++) Bds *= B;
+    for (int k = ds; k < D; k++) Brest *= B;
+    if (Bds >= std::ldexp(1.0L, 24) || Brest >= std::ldexp(1.0L, 24)) return false;
+    int ell = 0;
+    while ((1LL << ell) < B) ell++;
+    dp.e = e;
+    dp.B = (int)B;
+    dp.D = D;
+    dp.h = h;
+    dp.ds = ds;
+    dp.halfB = (int)half;
+    dp.z32 = Zmax < std::ldexp(1.0L, 31) ? 1 : 0;
+    dp.shift = 24 + ell;
+    dp.magic = (uint32_t)(((1ULL << (24 + ell)) / (unsigned long long)B) + 1);
+    dp.Qp = (u64)Q;
+    dp.Bd = (double)B;
+    dp.Qd = (double)dp.Qp;
+    dp.invQ = 1.0 / dp.Qd;
+    long double BH = 1, Bh = 1, bias = 0, pw = 1;
+    for (int k = 0; k < D - h; k++) BH *= B;
+    for (int k = 0; k < h; k++) Bh *= B;
+    for (int k = 0; k < D; k++) {
+        bias += half * pw;
+        pw *= B;
+    }
+    dp.BHd = (double)BH;
+    dp.invBH = 1.0 / dp.BHd;
+    dp.Bh = (double)Bh;
+    dp.Bsplit = (double)Bds;
+    dp.invBsplit = 1.0 / dp.Bsplit;
+    dp.bias = (double)bias;
+    return true;
+}
+
+void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out) {
+    const int D = dp.D, T = fam.tgt.count, half = (dp.B - 1) / 2;
+    const long long B = dp.B, Q = (long long)dp.Qp;
+    std::vector<int8_t> dig((size_t)fam.nsrc * T * D);
+    for (int r = 0; r < fam.nsrc; r++)
+        for (int k = 0; k < T; k++) {
+            long long x = (long long)it.psi[(size_t)r * T + k];
+            if (x > Q / 2) x -= Q;
+            for (int i = 0; i < D; i++) {
+                long long d = ((x % B) + B) % B;
+                if (d > half) d -= B;
+                dig[((size_t)r * T + k) * D + i] = (int8_t)d;
+                x = (x - d) / B;
+            }
+        }
+    for (int rt = 0; rt < nrt; rt++)
+        for (int i = 0; i < D; i++)
+            for (int kb = 0; kb < nkb; kb++)
+                for (int lane = 0; lane < 64; lane++)
+                    for (int j = 0; j < 16; j++) {
+                        const int row = 32 * rt + lane % 32, k = 32 * kb + (lane / 32) * 16 + j;
+                        int8_t v = (row < fam.nsrc && k < T) ? dig[((size_t)row * T + k) * D + i] : 0;
+                        out[((((size_t)rt * D + i) * nkb + kb) * 64 + lane) * 16 + j] = v;
+                    }
 }
 
 // ------------------------------------------------------------------ chunk counter

@@ -102,6 +102,7 @@ struct ItemSetup {
     std::vector<int> col_prec;       // M - col_shift
     std::vector<u64> col_unit;       // unit part of (p s_m - 1)!/(n-1)! mod q
     int64_t column_steps = 0, chunks = 0;
+    std::vector<int8_t> apack;       // psi digits for the MFMA kernel (empty if unused)
     int nchain() const { return (int)chain_g.size(); }
 };
 
@@ -116,6 +117,21 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
 // Unscale the device result Y (b x b mod q) and recover Q(T).
 cr_status finish_item(const Family &fam, const ItemSetup &it, const u64 *Y, u64 *frob,
                       int32_t *col_pole, int32_t *col_prec, int64_t *lpoly, std::string &err);
+
+// Parameters of the int8-digit representation of Z/Q' used by the MFMA kernel
+// (Q' = B^D, B = p^e <= 255 odd, balanced digits; see kernels_mfma.hip).
+struct DigitParams {
+    int e = 0, B = 0, D = 0, h = 0, ds = 0, halfB = 0, z32 = 0, shift = 0;
+    uint32_t magic = 0;
+    u64 Qp = 0;
+    double Bd = 0, Qd = 0, invQ = 0, BHd = 0, invBH = 0, Bh = 0, Bsplit = 0, invBsplit = 0, bias = 0;
+};
+// Chooses B, D and the Horner split h so that every recombination is exact in
+// fp64 and the weighted gather fits in 64 bits.  Returns false if no choice does.
+bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams &dp);
+// psi digits in v_mfma_i32_32x32x32_i8 A-fragment order:
+// out[(((rt*D + i)*nkb + kb)*64 + lane)*16 + j] = digit i of psi[32 rt + lane%32][32 kb + (lane/32)*16 + j]
+void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out);
 
 // Depth-first chunk schedule statistics of one chain (host mirror of the device
 // policy, used for counters only).

@@ -1,0 +1,351 @@
+// Exact int8-digit MFMA kernel for the controlled-reduction recurrence (gfx950).
+//
+// Same mathematics as k_reduce_chains (kernels.hip): each chain is one
+// Frobenius start term reduced one pole order per step with
+//   t  = psi[:, cols(v)] w                      (the decomposition of Proposition 3.3)
+//   w' = sum_i (u_i + r_i + [i not in S]) t[src(r, i)]   (explicit R_{u,v}, Section 3.1)
+// but t is computed for 32 chains at once as an integer matrix product on the
+// matrix cores: the chain vectors are scattered into the target space of J_S
+// (row v + g - 1_S), so chains with different directions share one product.
+//
+// Arithmetic: residues of Z/Q', Q' = B^D, B = p^e (B odd, B <= 169), held as
+// D balanced base-B digits in int8.  psi (D digits, rows = J_S sources, cols =
+// J_S targets) stays in VGPRs for the whole kernel; the 32 chain vectors are
+// D int8 digit planes in LDS.  For each digit position k < D the products
+// psi_i * X_j with i + j = k accumulate exactly in int32 (v_mfma_i32_32x32x32_i8);
+// positions >= D are multiples of Q' and are skipped.  The D partial sums of
+// each entry are recombined exactly in fp64 (Horner in two halves), reduced
+// mod Q', gathered with the small integer weights, reduced again and split
+// back into balanced digits for the next step.  Q' is a power of p that is a
+// multiple of p^M, so the final values reduced mod p^M are the exact ones.
+#include <hip/hip_runtime.h>
+
+#include "device_layout.hpp"
+
+namespace crf {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kCT = 32;  // chains per workgroup (one MFMA column tile)
+
+__device__ __forceinline__ double mod_fp(double x, double Q, double invQ) {
+    // exact for |x| < 2^53 and Q < 2^52: the fma result is the exact remainder
+    double qt = floor(x * invQ);
+    double r = fma(-qt, Q, x);
+    if (r < 0) r += Q;
+    if (r >= Q) r -= Q;
+    return r;
+}
+
+// Algorithm 3 (greedy v) and the depth-first chunk length (largest k with
+// U - k v >= 0, capped by the remaining pole orders).
+__device__ static void choose_chunk2(const DevFamily &fam, const int *U, int poles_left, int *v, int &dir, int &k) {
+    int left = fam.d;
+    for (int i = 0; i < fam.nv; i++) v[i] = 0;
+    for (int s = 0; s < fam.nv && left > 0; s++)
+        if (((fam.smask >> s) & 1u) && U[s] != 0) {
+            v[s] = 1;
+            left--;
+        }
+    while (left > 0) {
+        bool moved = false;
+        for (int m = 0; m < fam.nv && left > 0; m++)
+            if (v[m] < U[m]) {
+                v[m]++;
+                left--;
+                moved = true;
+            }
+        if (!moved) break;
+    }
+    k = poles_left;
+    for (int i = 0; i < fam.nv; i++)
+        if (v[i]) k = min(k, U[i] / v[i]);
+    dir = -1;
+    for (int t = 0; t < fam.ndir && dir < 0; t++) {
+        bool eq = true;
+        for (int i = 0; i < fam.nv; i++) eq = eq && (fam.dirs[t * fam.nv + i] == v[i]);
+        if (eq) dir = t;
+    }
+}
+
+constexpr int kTabCap = 2048;  // LDS capacity for colmap (ndir x s) entries
+constexpr int kGCap = 512;     // LDS capacity for gsrc / gw (s x nv) entries
+
+// Dynamic LDS layout (bytes):
+//   X   : D digit planes x 32 chains x XS     int8  (chain vectors in the J_S target space)
+//   Sb  : D positions x nsrc rows x 32 chains int32 (digit-position sums of t = psi x)
+//   tables (colmap, gsrc, gw) and per-chain state
+template <int NKB, int D>
+__host__ __device__ constexpr size_t mfma_x_bytes() {
+    return (size_t)D * kCT * (NKB * 32 + 16);
+}
+
+size_t mfma_lds_bytes_rt(int nkb, int D, int nsrc) {
+    return (size_t)D * kCT * (nkb * 32 + 16) + (size_t)D * nsrc * kCT * 4 + kTabCap * 2 + 2 * kGCap * 2 +
+           (size_t)kCT * 24 * 4;
+}
+
+template <int NRT, int NKB, int D>
+__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma(DevFamily fam, const DevDigitItem *__restrict__ items,
+                                                          const DevTile *__restrict__ tiles,
+                                                          const int16_t *__restrict__ cu,
+                                                          const int32_t *__restrict__ cg,
+                                                          const int32_t *__restrict__ cpole,
+                                                          uint64_t *__restrict__ hbuf, int *__restrict__ err) {
+    constexpr int K = NKB * 32;
+    constexpr int XS = K + 16;  // bytes per (digit, chain) row of X
+    constexpr int NT = 64 * NRT;
+    constexpr int NGRP = NT / kCT;  // phase-3 row groups
+    constexpr int DS = (D + 1) / 2;  // digit split: x = x_hi B^DS + x_lo
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int s = fam.s, nv = fam.nv, nsrc = fam.nsrc, F = fam.F;
+    const int n = fam.n;
+    int8_t *X = reinterpret_cast<int8_t *>(lds);
+    int *Sb = reinterpret_cast<int *>(lds + mfma_x_bytes<NKB, D>());
+    int16_t *colmapL = reinterpret_cast<int16_t *>(Sb + (size_t)D * nsrc * kCT);
+    int16_t *gsrcL = colmapL + kTabCap;
+    int16_t *gwL = gsrcL + kGCap;
+    int *U = reinterpret_cast<int *>(gwL + kGCap);
+    int *V = U + kCT * 8;
+    int *Dir = V + kCT * 8;
+    int *Kleft = Dir + kCT;
+    int *Pole = Kleft + kCT;
+    int *Act = Pole + kCT;
+
+    const DevTile tile = tiles[blockIdx.x];
+    const DevDigitItem it = items[tile.item];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nch = tile.count;
+
+    // psi digits of this wave's 32 source rows, resident for the whole kernel
+    v4i A[D][NKB];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int kb = 0; kb < NKB; kb++)
+            A[i][kb] = *reinterpret_cast<const v4i *>(it.apack + ((((size_t)wave * D + i) * NKB + kb) * 64 + lane) * 16);
+    for (int idx = tid; idx < fam.ndir * s; idx += NT) colmapL[idx] = fam.colmap[idx];
+    for (int idx = tid; idx < s * nv; idx += NT) {
+        gsrcL[idx] = fam.gsrc[idx];
+        gwL[idx] = fam.gw[idx];
+    }
+    for (int idx = tid; idx < (int)(mfma_x_bytes<NKB, D>() / 16); idx += NT)
+        reinterpret_cast<v4i *>(X)[idx] = v4i{0, 0, 0, 0};
+    for (int idx = tid; idx < nch * F; idx += NT) hbuf[(size_t)tile.chain0 * F + idx] = 0;
+    __syncthreads();
+    if (tid < nch) {
+        const int g = tile.chain0 + tid;
+        for (int i = 0; i < nv; i++) U[tid * 8 + i] = cu[(size_t)g * nv + i];
+        Pole[tid] = cpole[g];
+        int d0, k0;
+        choose_chunk2(fam, &U[tid * 8], Pole[tid] - n, &V[tid * 8], d0, k0);
+        if (d0 < 0 || k0 < 1) {
+            atomicOr(err, 1);
+            d0 = 0;
+            Pole[tid] = n;
+        }
+        Dir[tid] = d0;
+        Kleft[tid] = k0;
+        const int col = colmapL[d0 * s + cg[g]];
+        if (col < 0) atomicOr(err, 2);
+        else X[tid * XS + col] = (int8_t)(1);  // balanced digits of 1: (1, 0, ..., 0)
+    }
+    __syncthreads();
+
+    const double Bd = it.Bd, Qd = it.Qd, invQ = it.invQ, BHd = it.BHd, invBH = it.invBH, Bh = it.Bh;
+    const double Bsplit = it.Bsplit, invBsplit = it.invBsplit, bias = it.bias;
+    const int h = it.h, Bi = it.B, halfB = it.halfB, shift = it.shift;
+    const uint32_t magic = it.magic;
+    const bool z32 = it.z32 != 0;
+    const int c3 = tid % kCT, g3 = tid / kCT;  // phase-3 chain and row group of this thread
+
+    for (int step = 0; step < tile.steps; step++) {
+        // ---- phase 1: digit products on the matrix cores; position sums to LDS
+        {
+            v16i acc[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) acc[k] = v16i{0};
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                v4i xb[NKB];
+#pragma unroll
+                for (int kb = 0; kb < NKB; kb++)
+                    xb[kb] = *reinterpret_cast<const v4i *>(X + (j * kCT + (lane & 31)) * XS + kb * 32 + (lane >> 5) * 16);
+#pragma unroll
+                for (int i = 0; i + j < D; i++)
+#pragma unroll
+                    for (int kb = 0; kb < NKB; kb++)
+                        acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], acc[i + j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int row = wave * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                if (row < nsrc)
+#pragma unroll
+                    for (int k = 0; k < D; k++) Sb[((size_t)k * nsrc + row) * kCT + (lane & 31)] = acc[k][r];
+            }
+        }
+        __syncthreads();
+        // ---- phase 2: chain bookkeeping; clear the digit planes
+        if (tid < nch) {
+            const int c = tid;
+            Act[c] = Pole[c] > n;
+            if (Act[c]) {
+                for (int i = 0; i < nv; i++) U[c * 8 + i] -= V[c * 8 + i];
+                Pole[c]--;
+                Kleft[c]--;
+                if (Pole[c] > n && Kleft[c] == 0) {
+                    int d0, k0;
+                    choose_chunk2(fam, &U[c * 8], Pole[c] - n, &V[c * 8], d0, k0);
+                    if (d0 < 0 || k0 < 1) {
+                        atomicOr(err, 1);
+                        d0 = 0;
+                        Pole[c] = n;
+                    }
+                    Dir[c] = d0;
+                    Kleft[c] = k0;
+                }
+            }
+        }
+        for (int idx = tid; idx < (int)(mfma_x_bytes<NKB, D>() / 16); idx += NT)
+            reinterpret_cast<v4i *>(X)[idx] = v4i{0, 0, 0, 0};
+        __syncthreads();
+        // ---- phase 3: Z_k[r] = sum_i (u_i + r_i + [i not in S]) S_k[src(r,i)]; w'[r] = sum_k Z_k B^k mod Q'
+        if (c3 < nch && Act[c3]) {
+            const int c = c3;
+            const bool more = Pole[c] > n;
+            const int16_t *cm = colmapL + Dir[c] * s;
+            int Ucur[8];
+            for (int i = 0; i < nv; i++) Ucur[i] = U[c * 8 + i];
+            for (int r = g3; r < s; r += NGRP) {
+                double z[D];
+                if (z32) {
+                    int zi[D];
+#pragma unroll
+                    for (int k = 0; k < D; k++) zi[k] = 0;
+                    for (int i = 0; i < nv; i++) {
+                        const int src = gsrcL[r * nv + i];
+                        if (src < 0) continue;
+                        const int wt = Ucur[i] + gwL[r * nv + i];
+#pragma unroll
+                        for (int k = 0; k < D; k++) zi[k] += wt * Sb[((size_t)k * nsrc + src) * kCT + c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < D; k++) z[k] = (double)zi[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < D; k++) z[k] = 0.0;
+                    for (int i = 0; i < nv; i++) {
+                        const int src = gsrcL[r * nv + i];
+                        if (src < 0) continue;
+                        const double wt = (double)(Ucur[i] + gwL[r * nv + i]);
+#pragma unroll
+                        for (int k = 0; k < D; k++) z[k] = fma(wt, (double)Sb[((size_t)k * nsrc + src) * kCT + c], z[k]);
+                    }
+                }
+                double lo = 0.0, hi = 0.0;
+#pragma unroll
+                for (int k = D - 1; k >= 0; k--) {
+                    if (k >= h) hi = fma(hi, Bd, z[k]);
+                    else lo = fma(lo, Bd, z[k]);
+                }
+                double x = mod_fp(lo, Qd, invQ);
+                x = fma(mod_fp(hi, BHd, invBH), Bh, x);
+                if (x >= Qd) x -= Qd;
+                if (x == 0.0) continue;
+                if (more) {
+                    const int col = cm[r];
+                    if (col < 0) {
+                        atomicOr(err, 2);
+                        continue;
+                    }
+                    // balanced digits of x: unsigned digits of x + (Q'-1)/2, minus (B-1)/2
+                    double xs = x + bias;
+                    if (xs >= Qd) xs -= Qd;
+                    double xh = floor(xs * invBsplit);
+                    double rl = fma(-xh, Bsplit, xs);
+                    if (rl < 0.0) {  // the rounded quotient was one too high
+                        rl += Bsplit;
+                        xh -= 1.0;
+                    } else if (rl >= Bsplit) {
+                        rl -= Bsplit;
+                        xh += 1.0;
+                    }
+                    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
+                    int8_t *xp = X + c * XS + col;
+#pragma unroll
+                    for (int j = 0; j < DS; j++) {
+                        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
+                        xp[j * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
+                        vl = qd;
+                    }
+#pragma unroll
+                    for (int j = DS; j < D; j++) {
+                        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
+                        xp[j * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
+                        vh = qd;
+                    }
+                } else {
+                    // pole n reached: numerator x^U g / x^S, reduced mod p^M
+                    int Ui = -1;
+                    for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
+                        bool eq = true;
+                        for (int i = 0; i < nv; i++) eq = eq && (fam.finU[a * nv + i] == Ucur[i]);
+                        if (eq) Ui = a;
+                    }
+                    const int f = Ui < 0 ? -1 : fam.finmap[Ui * s + r];
+                    if (f < 0) atomicOr(err, 4);
+                    else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)x % it.q;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
+    nrt = (fam.nsrc + 31) / 32;
+    nkb = (fam.T + 31) / 32;
+    return ((nrt == 2 && nkb == 2) || (nrt == 3 && nkb == 3)) && fam.ndir * fam.s <= kTabCap &&
+           fam.s * fam.nv <= kGCap && fam.nv <= 8;
+}
+
+bool mfma_supports_digits(int D) { return D == 3 || D == 5 || D == 6 || D == 8 || D == 10; }
+
+template <int R, int KB, int DD>
+static hipError_t launch_one(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                             const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int *err,
+                             hipStream_t stream) {
+    const size_t lds = mfma_lds_bytes_rt(KB, DD, fam.nsrc);
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_mfma<R, KB, DD>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce_mfma<R, KB, DD>), dim3(ntiles), dim3(64 * R), lds, stream, fam, items, tiles, cu, cg,
+                       cpole, hbuf, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int *err,
+                              int D, hipStream_t stream) {
+    if (ntiles == 0) return hipSuccess;
+    int nrt, nkb;
+    if (!mfma_shape(fam, nrt, nkb)) return hipErrorInvalidValue;
+#define CRF_LAUNCH(R, KB, DD) \
+    if (nrt == R && nkb == KB && D == DD) return launch_one<R, KB, DD>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, err, stream);
+    CRF_LAUNCH(2, 2, 3)
+    CRF_LAUNCH(2, 2, 5)
+    CRF_LAUNCH(2, 2, 6)
+    CRF_LAUNCH(2, 2, 8)
+    CRF_LAUNCH(2, 2, 10)
+    CRF_LAUNCH(3, 3, 3)
+    CRF_LAUNCH(3, 3, 5)
+    CRF_LAUNCH(3, 3, 6)
+    CRF_LAUNCH(3, 3, 8)
+    CRF_LAUNCH(3, 3, 10)
+#undef CRF_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace crf

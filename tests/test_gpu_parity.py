@@ -18,17 +18,46 @@ from tests.gpu_common import assert_item_matches_oracle, run_batch, workload_ite
 pytestmark = pytest.mark.gpu
 
 
-def test_quartic_curve_f7():
+ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_quartic_curve_f7(engine):
     items = workload_items("quartic_curve_f7", [0])
-    res = run_batch(3, 4, items)
+    res = run_batch(3, 4, items, engine=engine)
+    assert res["stats"].engine == (0 if engine == C.ENGINE_AUTO else 1)
     assert_item_matches_oracle(res, 0, 3, 4, *items[0])
 
 
-def test_quintic_curves_mixed_primes():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_quintic_curves_mixed_primes(engine):
     items = workload_items("quintic_curves_mixed", range(6))
-    res = run_batch(3, 5, items)
+    res = run_batch(3, 5, items, engine=engine)
+    assert res["stats"].engine == (0 if engine == C.ENGINE_AUTO else 1)
     for i, (p, c) in enumerate(items):
         assert_item_matches_oracle(res, i, 3, 5, p, c)
+
+
+def test_every_quintic_prime_both_engines():
+    """One curve for each prime of the mixed workload (11..47): every digit base
+    (B = 121, 169, then B = p) against the oracle, both kernels."""
+    from tests.gpu_common import oracle_smooth
+    from paper_2602_24155_amd import workload
+    acc = oracle_smooth(3, 5)
+    items = []
+    for p in (11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47):
+        rng = np.random.default_rng(p)
+        while True:
+            c = [int(x) for x in rng.integers(0, p, size=21)]
+            if acc(p, c):
+                items.append((p, c))
+                break
+    a = run_batch(3, 5, items)
+    b = run_batch(3, 5, items, engine=C.ENGINE_VALU)
+    assert a["stats"].engine == 0 and b["stats"].engine == 1
+    for i, (p, c) in enumerate(items):
+        assert_item_matches_oracle(a, i, 3, 5, p, c)
+        assert_item_matches_oracle(b, i, 3, 5, p, c)
 
 
 def test_quintic_curves_p31():
@@ -85,3 +114,13 @@ def test_full_size_headline_batch():
             assert count_projective(from_coeffs(3, 5, c), 3, p, 1) == p + 1 + a[1]
     for i in (0, 100, 255):
         assert_item_matches_oracle(res, i, 3, 5, *items[i])
+
+
+def test_full_size_engines_agree():
+    """The MFMA and VALU kernels give bit-identical results on the 256-curve batch."""
+    items = workload_items("quintic_curves_p31", range(256))
+    a = run_batch(3, 5, items)
+    b = run_batch(3, 5, items, engine=C.ENGINE_VALU)
+    assert a["stats"].engine == 0 and b["stats"].engine == 1
+    assert np.array_equal(a["scaled"], b["scaled"])
+    assert a["lpoly"] == b["lpoly"]
