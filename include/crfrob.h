@@ -72,8 +72,10 @@ typedef struct {
     int32_t policy;   /* cr_policy */
     int32_t r;        /* relative precision override; 0 = derive (header comment) */
     int32_t n_series; /* series order override N_m for every m; 0 = r + 1 */
-    int32_t engine;   /* reduction kernel: 0 = auto (int8-digit MFMA kernel when the family's
-                         tables fit it, else the 64-bit VALU kernel), 1 = 64-bit VALU kernel */
+    int32_t engine;   /* reduction kernel: 0 = auto (int8-digit MFMA kernel with the gather on
+                         the accumulators when the family's tables fit it, else the 64-bit VALU
+                         kernel), 1 = 64-bit VALU kernel, 2 = int8-digit MFMA kernel with the
+                         gather through LDS */
 } cr_family;
 
 /* Per-call statistics (all counts are summed over the batch). */
@@ -86,7 +88,7 @@ typedef struct {
     double reduce_ms;      /* device time of the chain-reduction kernel alone (HIP events) */
     double assemble_ms;    /* device time of the Griffiths-Dwork assembly kernel alone */
     double finish_ms;      /* host unscaling and L-polynomial recovery */
-    int32_t engine;        /* kernel that ran: 0 = int8-digit MFMA, 1 = 64-bit VALU */
+    int32_t engine;        /* kernel that ran: 0 / 2 = int8-digit MFMA (register / LDS gather), 1 = 64-bit VALU */
     int32_t pad_;
 } cr_stats;
 

@@ -75,7 +75,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-ENGINE_AUTO, ENGINE_VALU = 0, 1
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS = 0, 1, 2
 
 
 def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO):

@@ -28,6 +28,9 @@ hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, c
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int *err,
                               int D, hipStream_t stream);
 bool mfma_supports_digits(int D);
+hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
+                               const uint32_t *slots, int *err, int D, hipStream_t stream);
 }  // namespace crf
 
 using namespace crf;
@@ -79,7 +82,9 @@ struct Arena {
 struct FamilyEntry {
     Family fam;
     std::vector<unsigned char> tables;  // packed device tables (host copy)
-    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU;
+    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots;
+    BinLayout bl;  // source-row placement for the register-gather MFMA kernel
+    bool bl_ok = false;
 };
 
 std::mutex g_mutex;
@@ -109,6 +114,12 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
     e->off_finmap = put(F.finmap.data(), F.finmap.size() * 2);
     e->off_dirs = put(F.dirs.exps.data(), F.dirs.exps.size());
     e->off_finU = put(F.finU.exps.data(), std::max<size_t>(F.finU.exps.size(), 1));
+    {
+        const int nrt = (F.nsrc + 31) / 32;
+        e->bl_ok = nrt >= 1 && nrt <= 3 && bin_layout(F, nrt, e->bl);
+        if (!e->bl_ok) e->bl.slot.assign(16, 0);
+        e->off_slots = put(e->bl.slot.data(), e->bl.slot.size() * 4);
+    }
     auto *raw = e.get();
     g_families.emplace(key, std::move(e));
     return raw;
@@ -153,6 +164,10 @@ bool check_family(const cr_family *fam, std::string &err) {
     }
     if (fam->nvars < 3 || fam->nvars > kMaxVars || fam->degree < 2 || fam->degree > 12) {
         err = "unsupported nvars/degree";
+        return false;
+    }
+    if (fam->engine < 0 || fam->engine > 2) {
+        err = "unknown engine";
         return false;
     }
     if (fam->policy != CR_POLICY_DEPTH_FIRST) {
@@ -259,7 +274,9 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     df.ndir = F.dirs.count;
     df.nfinU = F.finU.count;
     int nrt = 0, nkb = 0;
-    const bool want_mfma = fam->engine == 0 && mfma_shape(df, nrt, nkb);
+    const bool want_mfma = (fam->engine == 0 || fam->engine == 2) && mfma_shape(df, nrt, nkb);
+    // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
+    const bool use_bins = fam->engine == 0 && fe->bl_ok;
     std::vector<ItemSetup> items(count);
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
@@ -278,7 +295,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
             if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, dps[i]) && mfma_supports_digits(dps[i].D)) {
                 it.apack.resize((size_t)nrt * dps[i].D * nkb * 1024);
-                pack_psi_digits(F, it, dps[i], nrt, nkb, it.apack.data());
+                pack_psi_digits(F, it, dps[i], nrt, nkb, it.apack.data(), use_bins ? &fe->bl : nullptr);
                 digit_ok[i] = 1;
             }
         }
@@ -450,13 +467,19 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     if (he == hipSuccess && use_mfma) {
         for (auto &g : groups) {
             if (he != hipSuccess) break;
-            he = launch_reduce_mfma(df, reinterpret_cast<const DevDigitItem *>(db + o_ditems),
-                                    reinterpret_cast<const DevTile *>(db + o_tiles) + g.second.first, g.second.second,
-                                    reinterpret_cast<const int16_t *>(db + o_cu),
-                                    reinterpret_cast<const int32_t *>(db + o_cg),
-                                    reinterpret_cast<const int32_t *>(db + o_cp),
-                                    reinterpret_cast<uint64_t *>(db + o_hbuf), reinterpret_cast<int *>(db + o_err),
-                                    g.first, stream);
+            const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + o_ditems);
+            const DevTile *gt = reinterpret_cast<const DevTile *>(db + o_tiles) + g.second.first;
+            const int16_t *cu = reinterpret_cast<const int16_t *>(db + o_cu);
+            const int32_t *cgp = reinterpret_cast<const int32_t *>(db + o_cg);
+            const int32_t *cp = reinterpret_cast<const int32_t *>(db + o_cp);
+            uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + o_hbuf);
+            int *errp = reinterpret_cast<int *>(db + o_err);
+            if (use_bins)
+                he = launch_reduce_mfma4(df, ditems, gt, g.second.second, cu, cgp, cp, hb64,
+                                         reinterpret_cast<const uint32_t *>(db + o_tables + fe->off_slots), errp,
+                                         g.first, stream);
+            else
+                he = launch_reduce_mfma(df, ditems, gt, g.second.second, cu, cgp, cp, hb64, errp, g.first, stream);
         }
     }
     else if (he == hipSuccess)
@@ -518,7 +541,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         stats->setup_ms = setup_ms;
         stats->device_ms = dev_ms;
         stats->reduce_ms = red_ms;
-        stats->engine = use_mfma ? 0 : 1;
+        stats->engine = use_mfma ? (use_bins ? 0 : 2) : 1;
         stats->assemble_ms = asm_ms;
         stats->finish_ms = finish_ms;
     }

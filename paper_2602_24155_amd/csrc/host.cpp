@@ -41,6 +41,21 @@ long long binom(int n, int k) {
 
 long long count_monomials(int nv, int deg) { return deg < 0 ? 0 : binom(deg + nv - 1, nv - 1); }
 
+namespace {
+// C(n, k) for 0 <= n < 96, 0 <= k <= 8 (monomial ranks of degree < 90 in <= 8 variables)
+struct BinomTable {
+    long long t[96][9];
+    BinomTable() {
+        for (int n = 0; n < 96; n++)
+            for (int k = 0; k < 9; k++) t[n][k] = binom(n, k);
+    }
+};
+const BinomTable &btab() {
+    static const BinomTable T;
+    return T;
+}
+}  // namespace
+
 void MonoSpace::init(int nvars, int degree) {
     nv = nvars;
     deg = degree;
@@ -71,10 +86,15 @@ int MonoSpace::rank(const int *e) const {
         sum += e[i];
     }
     if (sum != deg) return -1;
+    // monomials before e: for each position i, those with the same prefix and a
+    // larger exponent at i; sum_{t > e_i} count(nv-i-1, rem-t) = C(rem - e_i - 1 + k, k)
+    // with k = nv - i - 1 (hockey-stick identity)
+    const BinomTable &B = btab();
     long long idx = 0;
     int rem = deg;
     for (int i = 0; i < nv - 1; i++) {
-        for (int t = e[i] + 1; t <= rem; t++) idx += count_monomials(nv - i - 1, rem - t);
+        const int k = nv - i - 1, top = rem - e[i] - 1 + k;
+        if (rem - e[i] > 0) idx += (top < 96 && k < 9) ? B.t[top][k] : binom(top, k);
         rem -= e[i];
     }
     return (int)idx;
@@ -307,13 +327,15 @@ static std::vector<int> nonpivot_columns_mod_p(std::vector<int> a, int rows, int
 // (A is not surjective mod p).
 static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int C, std::vector<u64> &X) {
     const int W = C + R;
+    const u64 q = mq.q;
     std::vector<u64> a((size_t)R * W, 0);
     for (int r = 0; r < R; r++) {
         std::memcpy(&a[(size_t)r * W], &A[(size_t)r * C], sizeof(u64) * C);
         a[(size_t)r * W + C + r] = 1;
     }
-    std::vector<int> piv(R, -1);
+    std::vector<int> piv(R, -1), nz;
     std::vector<char> used(C, 0);
+    nz.reserve(W);
     for (int r = 0; r < R; r++) {
         u64 *row = &a[(size_t)r * W];
         int c = -1;
@@ -324,16 +346,28 @@ static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int 
             }
         if (c < 0) return false;
         u64 inv = mq.inv(row[c]);
+        nz.clear();
         for (int k = 0; k < W; k++)
-            if (row[k]) row[k] = mq.mul(row[k], inv);
+            if (row[k]) {
+                row[k] = mq.mul(row[k], inv);
+                nz.push_back(k);
+            }
         for (int r2 = 0; r2 < R; r2++) {
             if (r2 == r) continue;
             u64 *o = &a[(size_t)r2 * W];
-            u64 f = o[c];
+            const u64 f = o[c];
             if (!f) continue;
-            u64 nf = mq.q - f;
-            for (int k = 0; k < W; k++)
-                if (row[k]) o[k] = mq.reduce((u128)o[k] + (u128)nf * row[k]);
+            // o -= f * row (mod q) with Shoup's precomputed quotient of f
+            const u64 nf = q - f;
+            const u64 fs = (u64)(((u128)nf << 64) / q);
+            for (int k : nz) {
+                const u64 x = row[k];
+                const u64 qh = (u64)(((u128)fs * x) >> 64);
+                u64 t = nf * x - qh * q;  // nf x mod q, in [0, 2q)
+                if (t >= q) t -= q;
+                t += o[k];
+                o[k] = t >= q ? t - q : t;
+            }
         }
         used[c] = 1;
         piv[r] = c;
@@ -453,7 +487,7 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                 }
         }
     }
-    {
+    if (smooth_only) {
         std::vector<int> Ji(J.size());
         for (size_t k = 0; k < J.size(); k++) Ji[k] = (int)(J[k] % p);
         if (rank_mod_p(Ji, fam.tgt.count, fam.nsrc, p) != fam.tgt.count) {
@@ -466,6 +500,47 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         }
     }
     if (smooth_only) return CR_OK;
+    // precision from the Hodge numbers of a smooth hypersurface of this degree
+    // (the basis computed below must have exactly these sizes)
+    std::vector<int> hodge_generic(n, 0);
+    for (int m = 1; m <= n; m++) {
+        const int k = d * m - n - 1;
+        long long hsz = 0;
+        for (int j = 0; j < nv; j++) {
+            const int kk = k - j * (d - 1);
+            if (kk < 0) break;
+            hsz += ((j & 1) ? -1 : 1) * binom(nv, j) * count_monomials(nv, kk);
+        }
+        hodge_generic[m - 1] = (int)hsz;
+    }
+    if (!choose_precision(p, n, hodge_generic, r_override, n_override, out.r, out.N, out.M, err)) return CR_EINVAL;
+    {
+        u128 q = 1;
+        for (int k = 0; k < out.M; k++) {
+            q *= (u64)p;
+            if (q >> 55) {
+                err = "p^M exceeds the 55-bit residues of this build";
+                return CR_EPRECISION;
+            }
+        }
+        out.mq.init((u64)q);
+    }
+    const ModQ &mq = out.mq;
+    // psi = right inverse of J_S over Z/q (Proposition 3.3 decomposition)
+    {
+        std::vector<u64> Jq(J.size());
+        for (size_t k = 0; k < J.size(); k++) Jq[k] = mq.from_int(J[k]);
+        std::vector<u64> X;
+        if (!right_inverse(mq, p, Jq, fam.tgt.count, fam.nsrc, X)) {
+            if (fam.nS == nv) {
+                err = "f is singular mod p";
+                return CR_ESINGULAR;
+            }
+            err = "f is not S-smooth";
+            return CR_ENOT_S_SMOOTH;
+        }
+        out.psi.swap(X);
+    }
     // basis B_m (Section 2.3)
     std::vector<std::vector<int>> Bm(n + 1);
     std::vector<MonoSpace> ksp(n + 1);
@@ -489,29 +564,9 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
     for (int m = 1; m <= n; m++)
         for (size_t k = 0; k < Bm[m].size(); k++) out.col_pole.push_back(m);
     out.b = (int)out.col_pole.size();
-    if (!choose_precision(p, n, out.hodge, r_override, n_override, out.r, out.N, out.M, err)) return CR_EINVAL;
-    {
-        u128 q = 1;
-        for (int k = 0; k < out.M; k++) {
-            q *= (u64)p;
-            if (q >> 55) {
-                err = "p^M exceeds the 55-bit residues of this build";
-                return CR_EPRECISION;
-            }
-        }
-        out.mq.init((u64)q);
-    }
-    const ModQ &mq = out.mq;
-    // psi = right inverse of J_S over Z/q (Proposition 3.3 decomposition)
-    {
-        std::vector<u64> Jq(J.size());
-        for (size_t k = 0; k < J.size(); k++) Jq[k] = mq.from_int(J[k]);
-        std::vector<u64> X;
-        if (!right_inverse(mq, p, Jq, fam.tgt.count, fam.nsrc, X)) {
-            err = "J_S not surjective mod p";
-            return CR_ENOT_S_SMOOTH;
-        }
-        out.psi.swap(X);
+    if (out.hodge != hodge_generic) {
+        err = "basis sizes differ from the Hodge numbers of a smooth hypersurface";
+        return CR_ESINGULAR;
     }
     // rho: pole-n numerators -> basis coordinates (Section 3.3, step (2))
     {
@@ -770,30 +825,82 @@ bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams 
     return true;
 }
 
-void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out) {
-    const int D = dp.D, T = fam.tgt.count, half = (dp.B - 1) / 2;
-    const long long B = dp.B, Q = (long long)dp.Qp;
-    std::vector<int8_t> dig((size_t)fam.nsrc * T * D);
-    for (int r = 0; r < fam.nsrc; r++)
-        for (int k = 0; k < T; k++) {
-            long long x = (long long)it.psi[(size_t)r * T + k];
-            if (x > Q / 2) x -= Q;
-            for (int i = 0; i < D; i++) {
-                long long d = ((x % B) + B) % B;
-                if (d > half) d -= B;
-                dig[((size_t)r * T + k) * D + i] = (int8_t)d;
-                x = (x - d) / B;
-            }
+bool bin_layout(const Family &fam, int nrt, BinLayout &bl) {
+    const int s = fam.g.count, nv = fam.nv;
+    struct Group {
+        int r;
+        std::vector<int> members;  // variable index i of each source row
+    };
+    std::vector<Group> groups;
+    for (int r = 0; r < s; r++) {
+        Group g{r, {}};
+        for (int i = 0; i < nv; i++)
+            if (fam.gsrc[(size_t)r * nv + i] >= 0) g.members.push_back(i);
+        if (!g.members.empty()) groups.push_back(g);
+    }
+    // largest groups first; bins of one wave filled alternately so both lane
+    // halves see the same sequence of group sizes whenever possible
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group &a, const Group &b) { return a.members.size() > b.members.size(); });
+    bl.nbins = 2 * nrt;
+    bl.slot_src.assign((size_t)bl.nbins * 16, -1);
+    bl.slot.assign((size_t)bl.nbins * 16, 0);
+    std::vector<int> fill(bl.nbins, 0);
+    int next = 0;
+    for (const Group &g : groups) {
+        const int sz = (int)g.members.size();
+        int b = -1;
+        for (int t = 0; t < bl.nbins && b < 0; t++) {
+            const int cand = (next + t) % bl.nbins;
+            if (fill[cand] + sz <= 16) b = cand;
         }
+        if (b < 0) return false;
+        next = (b + 1) % bl.nbins;
+        for (int m = 0; m < sz; m++) {
+            const int i = g.members[m], j = fill[b]++;
+            const int src = fam.gsrc[(size_t)g.r * nv + i];
+            const int gwv = fam.gw[(size_t)g.r * nv + i];
+            bl.slot_src[(size_t)b * 16 + j] = src;
+            bl.slot[(size_t)b * 16 + j] = 1u | ((m == sz - 1) ? 2u : 0u) | ((uint32_t)i << 2) |
+                                          ((uint32_t)gwv << 5) | ((uint32_t)g.r << 16);
+        }
+    }
+    return true;
+}
+
+void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out,
+                     const BinLayout *bl) {
+    const int D = dp.D, T = fam.tgt.count, half = (dp.B - 1) / 2;
+    const long long B = dp.B;
+    const u64 Q = dp.Qp, bias = (Q - 1) / 2;
+    std::vector<int8_t> dig((size_t)fam.nsrc * T * D);
+    for (size_t e = 0; e < (size_t)fam.nsrc * T; e++) {
+        // balanced digits of x = unsigned digits of (x + (Q-1)/2) mod Q, minus (B-1)/2
+        u64 x = it.psi[e] + bias;
+        if (x >= Q) x -= Q;
+        for (int i = 0; i < D; i++) {
+            const u64 qd = x / (u64)B;
+            dig[e * D + i] = (int8_t)((int)(x - qd * (u64)B) - half);
+            x = qd;
+        }
+    }
     for (int rt = 0; rt < nrt; rt++)
         for (int i = 0; i < D; i++)
             for (int kb = 0; kb < nkb; kb++)
-                for (int lane = 0; lane < 64; lane++)
-                    for (int j = 0; j < 16; j++) {
-                        const int row = 32 * rt + lane % 32, k = 32 * kb + (lane / 32) * 16 + j;
-                        int8_t v = (row < fam.nsrc && k < T) ? dig[((size_t)row * T + k) * D + i] : 0;
-                        out[((((size_t)rt * D + i) * nkb + kb) * 64 + lane) * 16 + j] = v;
+                for (int lane = 0; lane < 64; lane++) {
+                    int row = 32 * rt + lane % 32;
+                    if (bl) {  // MFMA row 32 rt + rho holds source row slot_src[bin][slot]
+                        const int rho = lane % 32, h = (rho >> 2) & 1, j = (rho >> 3) * 4 + (rho & 3);
+                        row = bl->slot_src[(size_t)(2 * rt + h) * 16 + j];
+                        if (row < 0) row = fam.nsrc;  // padding: zero row
                     }
+                    const int k0 = 32 * kb + (lane / 32) * 16;
+                    int8_t *dst = out + ((((size_t)rt * D + i) * nkb + kb) * 64 + lane) * 16;
+                    for (int j = 0; j < 16; j++) {
+                        const int k = k0 + j;
+                        dst[j] = (row < fam.nsrc && k < T) ? dig[((size_t)row * T + k) * D + i] : 0;
+                    }
+                }
 }
 
 // ------------------------------------------------------------------ chunk counter

@@ -129,9 +129,23 @@ struct DigitParams {
 // Chooses B, D and the Horner split h so that every recombination is exact in
 // fp64 and the weighted gather fits in 64 bits.  Returns false if no choice does.
 bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams &dp);
+// Placement of the J_S source rows in the MFMA accumulator layout so that every
+// output r of the weighted gather finds all its source rows src(r, i) in ONE
+// lane.  Lane half h of wave w holds rows 32 w + (j/4)*8 + h*4 + (j%4),
+// j = 0..15 ("bin" 2 w + h, "slot" j).  Each source row feeds exactly one
+// output (r -> r - 1_S + [i in S] e_i is injective), so the rows are
+// partitioned into groups, one per output, packed whole into bins.
+struct BinLayout {
+    int nbins = 0;
+    std::vector<int> slot_src;    // nbins x 16: source row or -1
+    std::vector<uint32_t> slot;   // nbins x 16: packed (valid | end << 1 | i << 2 | gw << 5 | r << 16)
+};
+bool bin_layout(const Family &fam, int nrt, BinLayout &bl);
+
 // psi digits in v_mfma_i32_32x32x32_i8 A-fragment order:
 // out[(((rt*D + i)*nkb + kb)*64 + lane)*16 + j] = digit i of psi[32 rt + lane%32][32 kb + (lane/32)*16 + j]
-void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out);
+void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out,
+                     const BinLayout *bl = nullptr);
 
 // Depth-first chunk schedule statistics of one chain (host mirror of the device
 // policy, used for counters only).

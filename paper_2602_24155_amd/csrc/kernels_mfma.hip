@@ -304,11 +304,305 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma(DevFamily fam, const D
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_reduce_mfma4: same arithmetic as k_reduce_mfma, with the J_S source rows
+// permuted (on the host) so that each output r of the weighted gather finds
+// all its source rows in ONE lane's 16 accumulator rows.  The gather then
+// runs on the MFMA accumulators directly: no LDS round trip for the digit
+// sums.  Chain state lives in registers (every lane of a chain computes it
+// identically) and the chain vectors are double buffered, so a step needs two
+// barriers: after the products (the current vectors may be cleared) and after
+// the new vectors are written.
+// slots[bin*16 + j] (bin = 2*wave + lane/32) packs: bit0 valid, bit1 ends the
+// output's group, bits 2-4 the variable i of the source row, bits 5-15 the
+// constant weight r_i + [i not in S], bits 16-31 the output r.
+__device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, const int8_t *dirsL, const int *U,
+                                                        int poles_left, int *v, int &dir, int &k) {
+    int left = fam.d;
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = 0;
+#pragma unroll
+    for (int sI = 0; sI < 8; sI++)
+        if (sI < fam.nv && left > 0 && ((fam.smask >> sI) & 1u) && U[sI] != 0) {
+            v[sI] = 1;
+            left--;
+        }
+    for (int guard = 0; guard < 64 && left > 0; guard++) {
+        bool moved = false;
+#pragma unroll
+        for (int m = 0; m < 8; m++)
+            if (m < fam.nv && left > 0 && v[m] < U[m]) {
+                v[m]++;
+                left--;
+                moved = true;
+            }
+        if (!moved) break;
+    }
+    k = poles_left;
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        if (i < fam.nv && v[i]) k = min(k, U[i] / v[i]);
+    dir = -1;
+    for (int t = 0; t < fam.ndir && dir < 0; t++) {
+        bool eq = true;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (i < fam.nv) eq = eq && (dirsL[t * fam.nv + i] == v[i]);
+        if (eq) dir = t;
+    }
+}
+
+template <int NRT, int NKB, int D>
+__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const DevDigitItem *__restrict__ items,
+                                                           const DevTile *__restrict__ tiles,
+                                                           const int16_t *__restrict__ cu,
+                                                           const int32_t *__restrict__ cg,
+                                                           const int32_t *__restrict__ cpole,
+                                                           uint64_t *__restrict__ hbuf,
+                                                           const uint32_t *__restrict__ slots, int *__restrict__ err) {
+    constexpr int K = NKB * 32;
+    constexpr int XS = K + 16;
+    constexpr int NT = 64 * NRT;
+    constexpr int XB = D * kCT * XS;  // bytes of one set of digit planes
+    constexpr int DS = (D + 1) / 2;
+    __shared__ __align__(16) int8_t Xbuf[2 * XB];
+    __shared__ int16_t colmapL[kTabCap];
+    __shared__ int8_t dirsL[512];
+    const int s = fam.s, nv = fam.nv, F = fam.F, n = fam.n;
+
+    const DevTile tile = tiles[blockIdx.x];
+    const DevDigitItem it = items[tile.item];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 31, half = lane >> 5, bin = 2 * wave + half;
+    const int nch = tile.count;
+
+    v4i A[D][NKB];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int kb = 0; kb < NKB; kb++)
+            A[i][kb] = *reinterpret_cast<const v4i *>(it.apack + ((((size_t)wave * D + i) * NKB + kb) * 64 + lane) * 16);
+    uint32_t sl[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) sl[j] = slots[bin * 16 + j];
+    for (int idx = tid; idx < fam.ndir * s; idx += NT) colmapL[idx] = fam.colmap[idx];
+    for (int idx = tid; idx < fam.ndir * nv; idx += NT) dirsL[idx] = fam.dirs[idx];
+    for (int idx = tid; idx < 2 * XB / 16; idx += NT) reinterpret_cast<v4i *>(Xbuf)[idx] = v4i{0, 0, 0, 0};
+    for (int idx = tid; idx < nch * F; idx += NT) hbuf[(size_t)tile.chain0 * F + idx] = 0;
+    __syncthreads();
+
+    // chain state (registers; identical in every lane of chain c)
+    int U[8], V[8], dir = 0, kleft = 0, pole = n;
+#pragma unroll
+    for (int i = 0; i < 8; i++) U[i] = V[i] = 0;
+    if (c < nch) {
+        const int g = tile.chain0 + c;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (i < nv) U[i] = cu[(size_t)g * nv + i];
+        pole = cpole[g];
+        int d0, k0;
+        choose_chunk_reg(fam, dirsL, U, pole - n, V, d0, k0);
+        if (d0 < 0 || k0 < 1) {
+            if (wave == 0 && half == 0) atomicOr(err, 1);
+            d0 = 0;
+            pole = n;
+        }
+        dir = d0;
+        kleft = k0;
+        if (wave == 0 && half == 0) {
+            const int col = colmapL[d0 * s + cg[g]];
+            if (col < 0) atomicOr(err, 2);
+            else Xbuf[c * XS + col] = (int8_t)1;  // balanced digits of 1
+        }
+    }
+    __syncthreads();
+
+    const double Bd = it.Bd, Qd = it.Qd, invQ = it.invQ, BHd = it.BHd, invBH = it.invBH, Bh = it.Bh;
+    const double Bsplit = it.Bsplit, invBsplit = it.invBsplit, bias = it.bias;
+    const int h = it.h, Bi = it.B, halfB = it.halfB, shift = it.shift;
+    const uint32_t magic = it.magic;
+    const bool z32 = it.z32 != 0;
+    int cur = 0;
+
+    for (int step = 0; step < tile.steps; step++) {
+        const int8_t *Xc = Xbuf + cur * XB;
+        int8_t *Xn = Xbuf + (cur ^ 1) * XB;
+        v16i acc[D];
+#pragma unroll
+        for (int k = 0; k < D; k++) acc[k] = v16i{0};
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            v4i xb[NKB];
+#pragma unroll
+            for (int kb = 0; kb < NKB; kb++)
+                xb[kb] = *reinterpret_cast<const v4i *>(Xc + (j * kCT + c) * XS + kb * 32 + half * 16);
+#pragma unroll
+            for (int i = 0; i + j < D; i++)
+#pragma unroll
+                for (int kb = 0; kb < NKB; kb++)
+                    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], acc[i + j], 0, 0, 0);
+        }
+        // bookkeeping of this lane's chain: exponent after the step, next direction
+        const bool act = pole > n;
+        int up[8], Vn[8], dirn = dir, kleftn = kleft - 1;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            up[i] = U[i] - (act ? V[i] : 0);
+            Vn[i] = V[i];
+        }
+        const bool more = act && pole - 1 > n;
+        if (more && kleftn == 0) {
+            int d0, k0;
+            choose_chunk_reg(fam, dirsL, up, pole - 1 - n, Vn, d0, k0);
+            if (d0 < 0 || k0 < 1) {
+                atomicOr(err, 1);
+                d0 = 0;
+                k0 = 1 << 30;
+            }
+            dirn = d0;
+            kleftn = k0;
+        }
+        __syncthreads();  // every wave has read the current digit planes
+        if (act) {
+            const int16_t *cm = colmapL + dirn * s;
+            int zi[D];
+            double zd[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                zi[k] = 0;
+                zd[k] = 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t w = sl[j];
+                if (!(w & 1u)) continue;
+                const int iv = (w >> 2) & 7;
+                int ui = up[0];
+#pragma unroll
+                for (int i = 1; i < 8; i++) ui = (iv == i) ? up[i] : ui;
+                const int wt = ui + (int)((w >> 5) & 2047u);
+                if (z32) {
+#pragma unroll
+                    for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < D; k++) zd[k] = fma((double)wt, (double)acc[k][j], zd[k]);
+                }
+                if (!(w & 2u)) continue;
+                // output r complete: w'[r] = sum_k Z_k B^k mod Q'
+                const int r = (int)(w >> 16);
+                double lo = 0.0, hi = 0.0;
+#pragma unroll
+                for (int k = D - 1; k >= 0; k--) {
+                    const double zk = z32 ? (double)zi[k] : zd[k];
+                    if (k >= h) hi = fma(hi, Bd, zk);
+                    else lo = fma(lo, Bd, zk);
+                    zi[k] = 0;
+                    zd[k] = 0.0;
+                }
+                double x = mod_fp(lo, Qd, invQ);
+                x = fma(mod_fp(hi, BHd, invBH), Bh, x);
+                if (x >= Qd) x -= Qd;
+                if (x == 0.0) continue;
+                if (more) {
+                    const int col = cm[r];
+                    if (col < 0) {
+                        atomicOr(err, 2);
+                        continue;
+                    }
+                    double xs = x + bias;
+                    if (xs >= Qd) xs -= Qd;
+                    double xh = floor(xs * invBsplit);
+                    double rl = fma(-xh, Bsplit, xs);
+                    if (rl < 0.0) {
+                        rl += Bsplit;
+                        xh -= 1.0;
+                    } else if (rl >= Bsplit) {
+                        rl -= Bsplit;
+                        xh += 1.0;
+                    }
+                    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
+                    int8_t *xp = Xn + c * XS + col;
+#pragma unroll
+                    for (int jd = 0; jd < DS; jd++) {
+                        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
+                        xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
+                        vl = qd;
+                    }
+#pragma unroll
+                    for (int jd = DS; jd < D; jd++) {
+                        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
+                        xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
+                        vh = qd;
+                    }
+                } else {
+                    int Ui = -1;
+                    for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
+                        bool eq = true;
+                        for (int i = 0; i < nv; i++) eq = eq && (fam.finU[a * nv + i] == up[i]);
+                        if (eq) Ui = a;
+                    }
+                    const int f = Ui < 0 ? -1 : fam.finmap[Ui * s + r];
+                    if (f < 0) atomicOr(err, 4);
+                    else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)x % it.q;
+                }
+            }
+        }
+        // clear the planes just consumed; they receive the vectors of the next step
+        int8_t *Xz = Xbuf + cur * XB;
+        for (int idx = tid; idx < XB / 16; idx += NT) reinterpret_cast<v4i *>(Xz)[idx] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            U[i] = up[i];
+            V[i] = Vn[i];
+        }
+        if (act) {
+            pole -= 1;
+            dir = dirn;
+            kleft = kleftn;
+        }
+        cur ^= 1;
+        __syncthreads();  // next digit planes complete
+    }
+}
+
 bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
     nrt = (fam.nsrc + 31) / 32;
     nkb = (fam.T + 31) / 32;
     return ((nrt == 2 && nkb == 2) || (nrt == 3 && nkb == 3)) && fam.ndir * fam.s <= kTabCap &&
            fam.s * fam.nv <= kGCap && fam.nv <= 8;
+}
+
+template <int R, int KB, int DD>
+static hipError_t launch_one4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
+                              const uint32_t *slots, int *err, hipStream_t stream) {
+    hipLaunchKernelGGL((k_reduce_mfma4<R, KB, DD>), dim3(ntiles), dim3(64 * R), 0, stream, fam, items, tiles, cu, cg,
+                       cpole, hbuf, slots, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
+                               const uint32_t *slots, int *err, int D, hipStream_t stream) {
+    if (ntiles == 0) return hipSuccess;
+    int nrt, nkb;
+    if (!mfma_shape(fam, nrt, nkb) || fam.ndir * fam.nv > 512) return hipErrorInvalidValue;
+#define CRF_LAUNCH4(R, KB, DD) \
+    if (nrt == R && nkb == KB && D == DD) return launch_one4<R, KB, DD>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream);
+    CRF_LAUNCH4(2, 2, 3)
+    CRF_LAUNCH4(2, 2, 5)
+    CRF_LAUNCH4(2, 2, 6)
+    CRF_LAUNCH4(2, 2, 8)
+    CRF_LAUNCH4(2, 2, 10)
+    CRF_LAUNCH4(3, 3, 3)
+    CRF_LAUNCH4(3, 3, 5)
+    CRF_LAUNCH4(3, 3, 6)
+    CRF_LAUNCH4(3, 3, 8)
+    CRF_LAUNCH4(3, 3, 10)
+#undef CRF_LAUNCH4
+    return hipErrorInvalidValue;
 }
 
 bool mfma_supports_digits(int D) { return D == 3 || D == 5 || D == 6 || D == 8 || D == 10; }

@@ -18,14 +18,14 @@ from tests.gpu_common import assert_item_matches_oracle, run_batch, workload_ite
 pytestmark = pytest.mark.gpu
 
 
-ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU]
+ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU, C.ENGINE_MFMA_LDS]
 
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_quartic_curve_f7(engine):
     items = workload_items("quartic_curve_f7", [0])
     res = run_batch(3, 4, items, engine=engine)
-    assert res["stats"].engine == (0 if engine == C.ENGINE_AUTO else 1)
+    assert res["stats"].engine == engine
     assert_item_matches_oracle(res, 0, 3, 4, *items[0])
 
 
@@ -33,7 +33,7 @@ def test_quartic_curve_f7(engine):
 def test_quintic_curves_mixed_primes(engine):
     items = workload_items("quintic_curves_mixed", range(6))
     res = run_batch(3, 5, items, engine=engine)
-    assert res["stats"].engine == (0 if engine == C.ENGINE_AUTO else 1)
+    assert res["stats"].engine == engine
     for i, (p, c) in enumerate(items):
         assert_item_matches_oracle(res, i, 3, 5, p, c)
 
@@ -52,12 +52,11 @@ def test_every_quintic_prime_both_engines():
             if acc(p, c):
                 items.append((p, c))
                 break
-    a = run_batch(3, 5, items)
-    b = run_batch(3, 5, items, engine=C.ENGINE_VALU)
-    assert a["stats"].engine == 0 and b["stats"].engine == 1
-    for i, (p, c) in enumerate(items):
-        assert_item_matches_oracle(a, i, 3, 5, p, c)
-        assert_item_matches_oracle(b, i, 3, 5, p, c)
+    runs = [run_batch(3, 5, items, engine=e) for e in ENGINES]
+    for e, res in zip(ENGINES, runs):
+        assert res["stats"].engine == e
+        for i, (p, c) in enumerate(items):
+            assert_item_matches_oracle(res, i, 3, 5, p, c)
 
 
 def test_quintic_curves_p31():
@@ -119,8 +118,8 @@ def test_full_size_headline_batch():
 def test_full_size_engines_agree():
     """The MFMA and VALU kernels give bit-identical results on the 256-curve batch."""
     items = workload_items("quintic_curves_p31", range(256))
-    a = run_batch(3, 5, items)
-    b = run_batch(3, 5, items, engine=C.ENGINE_VALU)
-    assert a["stats"].engine == 0 and b["stats"].engine == 1
-    assert np.array_equal(a["scaled"], b["scaled"])
-    assert a["lpoly"] == b["lpoly"]
+    runs = [run_batch(3, 5, items, engine=e) for e in ENGINES]
+    for e, res in zip(ENGINES, runs):
+        assert res["stats"].engine == e
+        assert np.array_equal(res["scaled"], runs[0]["scaled"])
+        assert res["lpoly"] == runs[0]["lpoly"]
