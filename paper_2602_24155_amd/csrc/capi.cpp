@@ -30,7 +30,8 @@ hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, c
 bool mfma_supports_digits(int D);
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                                const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
-                               const uint32_t *slots, int *err, int D, hipStream_t stream);
+                               const uint32_t *slots, int *err, int D, bool z32, hipStream_t stream);
+bool mfma4_supports(const DevFamily &fam, int D);
 }  // namespace crf
 
 using namespace crf;
@@ -326,6 +327,8 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     for (int i : live) nchain += items[i].nchain();
     bool use_mfma = want_mfma;
     for (int li = 0; li < nlive && use_mfma; li++) use_mfma = digit_ok[live[li]] != 0;
+    for (int li = 0; li < nlive && use_mfma && use_bins; li++)
+        if (!mfma4_supports(df, dps[live[li]].D)) use_mfma = false;  // packed for the other layout: fall back
     int ct = 32;
     if (!use_mfma) {
         while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
@@ -333,10 +336,10 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     }
     // tiles of ct chains of one item; for the MFMA kernel grouped by digit count D
     std::vector<DevTile> tiles;
-    std::vector<std::pair<int, std::pair<int, int>>> groups;  // (D, (first tile, count))
+    std::vector<std::pair<int, std::pair<int, int>>> groups;  // (D + 100 z32, (first tile, count))
     std::vector<int> dvals;
     if (use_mfma) {
-        for (int li = 0; li < nlive; li++) dvals.push_back(dps[live[li]].D);
+        for (int li = 0; li < nlive; li++) dvals.push_back(dps[live[li]].D + 100 * dps[live[li]].z32);
         std::sort(dvals.begin(), dvals.end());
         dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
     } else {
@@ -345,7 +348,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     for (int D : dvals) {
         const int first = (int)tiles.size();
         for (int li = 0; li < nlive; li++) {
-            if (use_mfma && dps[live[li]].D != D) continue;
+            if (use_mfma && dps[live[li]].D + 100 * dps[live[li]].z32 != D) continue;
             const ItemSetup &it = items[live[li]];
             for (int c0 = 0; c0 < it.nchain(); c0 += ct) {
                 DevTile t{};
@@ -474,12 +477,14 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             const int32_t *cp = reinterpret_cast<const int32_t *>(db + o_cp);
             uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + o_hbuf);
             int *errp = reinterpret_cast<int *>(db + o_err);
+            const int Dg = g.first % 100;
+            const bool z32g = g.first >= 100;
             if (use_bins)
                 he = launch_reduce_mfma4(df, ditems, gt, g.second.second, cu, cgp, cp, hb64,
                                          reinterpret_cast<const uint32_t *>(db + o_tables + fe->off_slots), errp,
-                                         g.first, stream);
+                                         Dg, z32g, stream);
             else
-                he = launch_reduce_mfma(df, ditems, gt, g.second.second, cu, cgp, cp, hb64, errp, g.first, stream);
+                he = launch_reduce_mfma(df, ditems, gt, g.second.second, cu, cgp, cp, hb64, errp, Dg, stream);
         }
     }
     else if (he == hipSuccess)

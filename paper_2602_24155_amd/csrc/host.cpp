@@ -832,39 +832,78 @@ bool bin_layout(const Family &fam, int nrt, BinLayout &bl) {
         std::vector<int> members;  // variable index i of each source row
     };
     std::vector<Group> groups;
+    int maxsz = 0;
     for (int r = 0; r < s; r++) {
         Group g{r, {}};
         for (int i = 0; i < nv; i++)
             if (fam.gsrc[(size_t)r * nv + i] >= 0) g.members.push_back(i);
-        if (!g.members.empty()) groups.push_back(g);
+        if (!g.members.empty()) {
+            maxsz = std::max(maxsz, (int)g.members.size());
+            groups.push_back(g);
+        }
     }
-    // largest groups first; bins of one wave filled alternately so both lane
-    // halves see the same sequence of group sizes whenever possible
-    std::stable_sort(groups.begin(), groups.end(),
-                     [](const Group &a, const Group &b) { return a.members.size() > b.members.size(); });
+    if (maxsz > 4) return false;
     bl.nbins = 2 * nrt;
+    // Every bin gets the same pattern of group slots (sizes 4, 3, 2, 1, largest
+    // first), so the group ends fall on the same accumulator slots in every
+    // lane and the per-output work never diverges.  Choose slot counts c_k with
+    // sum k c_k <= 16 such that groups of size >= k fit in slots of size >= k.
+    std::vector<int> G(5, 0);
+    for (auto &g : groups) G[g.members.size()]++;
+    int best[5] = {0, 0, 0, 0, 0}, bestslots = 1 << 30;
+    for (int c4 = 0; c4 <= 4; c4++)
+        for (int c3 = 0; c3 <= 5; c3++)
+            for (int c2 = 0; c2 <= 8; c2++)
+                for (int c1 = 0; c1 <= 16; c1++) {
+                    if (4 * c4 + 3 * c3 + 2 * c2 + c1 > 16) continue;
+                    const int nb = bl.nbins;
+                    if (nb * c4 < G[4] || nb * (c4 + c3) < G[4] + G[3] || nb * (c4 + c3 + c2) < G[4] + G[3] + G[2] ||
+                        nb * (c4 + c3 + c2 + c1) < G[4] + G[3] + G[2] + G[1])
+                        continue;
+                    const int slots = c4 + c3 + c2 + c1;
+                    if (slots < bestslots) {
+                        bestslots = slots;
+                        best[4] = c4, best[3] = c3, best[2] = c2, best[1] = c1;
+                    }
+                }
+    if (bestslots == (1 << 30)) return false;
+    std::vector<int> pattern;  // slot sizes of one bin, largest first
+    for (int k = 4; k >= 1; k--)
+        for (int t = 0; t < best[k]; t++) pattern.push_back(k);
     bl.slot_src.assign((size_t)bl.nbins * 16, -1);
     bl.slot.assign((size_t)bl.nbins * 16, 0);
-    std::vector<int> fill(bl.nbins, 0);
-    int next = 0;
+    // group slots in order (slot position, bin): fill the largest groups first,
+    // round-robin over bins so the outputs spread evenly across lanes
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group &a, const Group &b) { return a.members.size() > b.members.size(); });
+    struct Slot {
+        int bin, start, size;
+        bool used;
+    };
+    std::vector<Slot> slots;
+    for (size_t pi = 0, start = 0; pi < pattern.size(); start += pattern[pi], pi++)
+        for (int b = 0; b < bl.nbins; b++) slots.push_back({b, (int)start, pattern[pi], false});
     for (const Group &g : groups) {
         const int sz = (int)g.members.size();
-        int b = -1;
-        for (int t = 0; t < bl.nbins && b < 0; t++) {
-            const int cand = (next + t) % bl.nbins;
-            if (fill[cand] + sz <= 16) b = cand;
-        }
-        if (b < 0) return false;
-        next = (b + 1) % bl.nbins;
+        Slot *pick = nullptr;
+        for (auto &sl : slots)  // smallest free slot that holds the group
+            if (!sl.used && sl.size >= sz && (!pick || sl.size < pick->size)) pick = &sl;
+        if (!pick) return false;
+        pick->used = true;
+        // rows at the END of the slot so that the group end is the slot end
+        const int first = pick->start + pick->size - sz;
         for (int m = 0; m < sz; m++) {
-            const int i = g.members[m], j = fill[b]++;
+            const int i = g.members[m], j = first + m;
             const int src = fam.gsrc[(size_t)g.r * nv + i];
             const int gwv = fam.gw[(size_t)g.r * nv + i];
-            bl.slot_src[(size_t)b * 16 + j] = src;
-            bl.slot[(size_t)b * 16 + j] = 1u | ((m == sz - 1) ? 2u : 0u) | ((uint32_t)i << 2) |
-                                          ((uint32_t)gwv << 5) | ((uint32_t)g.r << 16);
+            bl.slot_src[(size_t)pick->bin * 16 + j] = src;
+            bl.slot[(size_t)pick->bin * 16 + j] = 1u | ((m == sz - 1) ? 2u : 0u) | ((uint32_t)i << 2) |
+                                                  ((uint32_t)gwv << 5) | ((uint32_t)g.r << 16);
         }
     }
+    // unused group slots still mark their end, so every lane runs the same code
+    for (auto &sl : slots)
+        if (!sl.used) bl.slot[(size_t)sl.bin * 16 + sl.start + sl.size - 1] |= 2u | (0xFFFFu << 16);
     return true;
 }
 

@@ -352,7 +352,7 @@ __device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, co
     }
 }
 
-template <int NRT, int NKB, int D>
+template <int NRT, int NKB, int D, int NV, bool Z32>
 __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const DevDigitItem *__restrict__ items,
                                                            const DevTile *__restrict__ tiles,
                                                            const int16_t *__restrict__ cu,
@@ -422,7 +422,6 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
     const double Bsplit = it.Bsplit, invBsplit = it.invBsplit, bias = it.bias;
     const int h = it.h, Bi = it.B, halfB = it.halfB, shift = it.shift;
     const uint32_t magic = it.magic;
-    const bool z32 = it.z32 != 0;
     int cur = 0;
 
     for (int step = 0; step < tile.steps; step++) {
@@ -480,9 +479,9 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
                 const int iv = (w >> 2) & 7;
                 int ui = up[0];
 #pragma unroll
-                for (int i = 1; i < 8; i++) ui = (iv == i) ? up[i] : ui;
+                for (int i = 1; i < NV; i++) ui = (iv == i) ? up[i] : ui;
                 const int wt = ui + (int)((w >> 5) & 2047u);
-                if (z32) {
+                if (Z32) {
 #pragma unroll
                     for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
                 } else {
@@ -492,10 +491,11 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
                 if (!(w & 2u)) continue;
                 // output r complete: w'[r] = sum_k Z_k B^k mod Q'
                 const int r = (int)(w >> 16);
+                if (r == 0xFFFF) continue;  // unused group slot
                 double lo = 0.0, hi = 0.0;
 #pragma unroll
                 for (int k = D - 1; k >= 0; k--) {
-                    const double zk = z32 ? (double)zi[k] : zd[k];
+                    const double zk = Z32 ? (double)zi[k] : zd[k];
                     if (k >= h) hi = fma(hi, Bd, zk);
                     else lo = fma(lo, Bd, zk);
                     zi[k] = 0;
@@ -574,31 +574,36 @@ bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
            fam.s * fam.nv <= kGCap && fam.nv <= 8;
 }
 
-template <int R, int KB, int DD>
+template <int R, int KB, int DD, bool ZZ>
 static hipError_t launch_one4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
                               const uint32_t *slots, int *err, hipStream_t stream) {
-    hipLaunchKernelGGL((k_reduce_mfma4<R, KB, DD>), dim3(ntiles), dim3(64 * R), 0, stream, fam, items, tiles, cu, cg,
-                       cpole, hbuf, slots, err);
+    hipLaunchKernelGGL((k_reduce_mfma4<R, KB, DD, 3, ZZ>), dim3(ntiles), dim3(64 * R), 0, stream, fam, items, tiles, cu,
+                       cg, cpole, hbuf, slots, err);
     return hipGetLastError();
+}
+
+bool mfma4_supports(const DevFamily &fam, int D) {
+    int nrt, nkb;
+    if (!mfma_shape(fam, nrt, nkb) || fam.nv != 3 || fam.ndir * fam.nv > 512) return false;
+    return (nrt == 2 && (D == 3 || D == 6)) || (nrt == 3 && (D == 5 || D == 8 || D == 10));
 }
 
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                                const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
-                               const uint32_t *slots, int *err, int D, hipStream_t stream) {
+                               const uint32_t *slots, int *err, int D, bool z32, hipStream_t stream) {
     if (ntiles == 0) return hipSuccess;
     int nrt, nkb;
-    if (!mfma_shape(fam, nrt, nkb) || fam.ndir * fam.nv > 512) return hipErrorInvalidValue;
-#define CRF_LAUNCH4(R, KB, DD) \
-    if (nrt == R && nkb == KB && D == DD) return launch_one4<R, KB, DD>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream);
+    if (!mfma4_supports(fam, D)) return hipErrorInvalidValue;
+    mfma_shape(fam, nrt, nkb);
+#define CRF_LAUNCH4(R, KB, DD)                                                                                          \
+    if (nrt == R && nkb == KB && D == DD) {                                                                             \
+        if (z32) return launch_one4<R, KB, DD, true>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream); \
+        return launch_one4<R, KB, DD, false>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream);       \
+    }
     CRF_LAUNCH4(2, 2, 3)
-    CRF_LAUNCH4(2, 2, 5)
     CRF_LAUNCH4(2, 2, 6)
-    CRF_LAUNCH4(2, 2, 8)
-    CRF_LAUNCH4(2, 2, 10)
-    CRF_LAUNCH4(3, 3, 3)
     CRF_LAUNCH4(3, 3, 5)
-    CRF_LAUNCH4(3, 3, 6)
     CRF_LAUNCH4(3, 3, 8)
     CRF_LAUNCH4(3, 3, 10)
 #undef CRF_LAUNCH4
