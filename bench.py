@@ -21,6 +21,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
+KERNEL_NAMES = {0: "k_reduce_mfma4", 1: "k_reduce_chains", 2: "k_reduce_mfma"}
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the reduction kernel from the committed rocprofv3
+    counters, if they were taken on the kernel source as it is now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_reduce_mfma4_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    prof = json.load(open(path))
+    src = open(os.path.join(ROOT, prof["kernel_source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != prof["kernel_source_sha256"]:
+        return None
+    return prof["traffic_bytes_per_launch"]
 
 
 def limbs_for(q):
@@ -69,7 +84,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="quintic_curves_p31")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (profiler calibration "
+                         "of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.empty(args.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the hypersurfaces of a batch are independent; see DESIGN.md for how it would shard)",
@@ -133,8 +160,9 @@ def main():
         "matvecs_per_s": st.column_steps / red_s,
         "breakdown_ms": {k: v / args.steps for k, v in tot.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_reduce_chains",
+                     "frac": achieved / INT8_PEAK_TOPS,
+                     "traffic": measured_traffic(args.workload) if st.engine == 0 else None,
+                     "kernel": KERNEL_NAMES.get(st.engine, "?"),
                      "work_per_column_step_int8_ops": work_per_colstep},
     }
     if not args.no_cpu_baseline:
