@@ -60,9 +60,23 @@ typedef enum {
  * each reduction step is an exact identity in cohomology and the
  * coordinates of a class are unique. */
 typedef enum {
-    CR_POLICY_DEPTH_FIRST = 0 /* Section 4.2: per term greedy v (Algorithm 3), largest chunk k
-                                 with v in V_full(u, k); never combines like terms */
+    CR_POLICY_DEPTH_FIRST = 0, /* Section 4.2: per term greedy v (Algorithm 3), largest chunk k
+                                  with v in V_full(u, k); never combines like terms */
+    CR_POLICY_P_CHUNK = 1,     /* Section 4.1: the terms of largest pole L are reduced to
+                                  max(L - p, n) by Algorithm 3 chunks, then like terms (equal
+                                  exponent u) are combined; repeat */
+    CR_POLICY_VAR_BY_VAR = 2,  /* Section 4.3: reduce every term until u_n = 0, combine, then
+                                  u_{n-1}, ..., u_0; the rest goes to pole n */
+    CR_POLICY_LEARNED = 3      /* the p-chunk phases with each term's direction chosen by a
+                                  trained MLP (cr_mlp_*), judged against the plain policies by
+                                  the game cost of Section 3.4 (falls back when it loses) */
 } cr_policy;
+
+/* Combining like terms (Section 3.4, second move of the game): a term is a
+ * vector w over Homog_{dn-n} times a row c of basis-column coefficients.  A
+ * group of terms with equal exponent u and active columns A is replaced by
+ * |A| vectors sum_j c_j[a] w_j (one per column a in A) when it holds more
+ * than |A| terms; smaller groups are left as they are. */
 
 /* A family of hypersurfaces that share nvars, degree and S; p may vary per item. */
 typedef struct {
@@ -80,15 +94,21 @@ typedef struct {
 
 /* Per-call statistics (all counts are summed over the batch). */
 typedef struct {
-    int64_t start_blocks;  /* distinct Frobenius start terms (x^S form exponents) */
-    int64_t column_steps;  /* s x s . s reduction products (the paper's unit M of Section 3.4) */
-    int64_t chunks;        /* reduction chunks (u, v, k) */
-    double setup_ms;       /* host setup wall time */
-    double device_ms;      /* device time of the reduction and assembly kernels */
-    double reduce_ms;      /* device time of the chain-reduction kernel alone (HIP events) */
-    double assemble_ms;    /* device time of the Griffiths-Dwork assembly kernel alone */
-    double finish_ms;      /* host unscaling and L-polynomial recovery */
-    int32_t engine;        /* kernel that ran: 0 / 2 = int8-digit MFMA (register / LDS gather), 1 = 64-bit VALU */
+    int64_t start_blocks;    /* distinct Frobenius start terms (x^S form exponents) */
+    int64_t column_steps;    /* s x s . s reduction products (the paper's unit M of Section 3.4) */
+    int64_t chunks;          /* reduction chunks (u, v, k): the startup cost S of Section 3.4 */
+    int64_t vectors;         /* vectors reduced (start terms and combined columns, every phase) */
+    int64_t merged_terms;    /* terms absorbed by combining like terms (cost D each) */
+    int64_t combined_groups; /* groups of like terms that were combined */
+    double setup_ms;         /* host setup and planning wall time */
+    double device_ms;        /* device time of the reduction, combine and assembly kernels */
+    double reduce_ms;        /* device time of the reduction kernels (HIP events) */
+    double combine_ms;       /* device time of the combine kernels */
+    double assemble_ms;      /* device time of the Griffiths-Dwork assembly kernel */
+    double finish_ms;        /* host unscaling and L-polynomial recovery */
+    int32_t engine;          /* kernel that ran: 0 / 2 = int8-digit MFMA (register / LDS gather), 1 = 64-bit VALU */
+    int32_t policy;          /* policy whose plan ran */
+    int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
     int32_t pad_;
 } cr_stats;
 
@@ -140,6 +160,13 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
                              const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
                              int32_t *col_pole, int32_t *col_prec, int64_t *lpoly,
                              int32_t *item_status, cr_stats *stats, void *hip_stream);
+
+/* Host-only planning of one hypersurface under fam->policy (no device work):
+ * fills start_blocks, column_steps, chunks, vectors, merged_terms,
+ * combined_groups, phases and policy of *stats (the game cost of Section 3.4
+ * is M column_steps + S chunks + D merged_terms).  Not available for
+ * CR_POLICY_LEARNED (whose plan needs the model): CR_EINVAL. */
+cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs, cr_stats *stats);
 
 /* Frees the library's cached device and host workspaces. */
 cr_status cr_release(void);

@@ -14,10 +14,10 @@ LIB_PATH = os.path.join(_HERE, "libcrfrob.so")
 
 CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
     CR_EPRECISION, CR_ENOMEM, CR_EDEVICE, CR_ESELFCHECK = range(10)
-CR_POLICY_DEPTH_FIRST = 0
+CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_release", "cr_last_error"]
+           "cr_frobenius_batch", "cr_policy_cost", "cr_release", "cr_last_error"]
 
 
 class cr_family(ctypes.Structure):
@@ -28,10 +28,13 @@ class cr_family(ctypes.Structure):
 
 class cr_stats(ctypes.Structure):
     _fields_ = [("start_blocks", ctypes.c_int64), ("column_steps", ctypes.c_int64),
-                ("chunks", ctypes.c_int64), ("setup_ms", ctypes.c_double),
-                ("device_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
+                ("chunks", ctypes.c_int64), ("vectors", ctypes.c_int64),
+                ("merged_terms", ctypes.c_int64), ("combined_groups", ctypes.c_int64),
+                ("setup_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double),
                 ("assemble_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
-                ("engine", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("policy", ctypes.c_int32),
+                ("phases", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class CrError(RuntimeError):
@@ -57,6 +60,7 @@ def lib():
         L.cr_check_smooth.argtypes = [P(cr_family), i32, P(u32), P(i32)]
         L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
                                          P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
+        L.cr_policy_cost.argtypes = [P(cr_family), i32, P(u32), P(cr_stats)]
         L.cr_release.argtypes = []
         L.cr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -145,6 +149,14 @@ def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise
         "status": st, "item_status": ist, "frob": frob, "scaled": scaled, "col_pole": pole,
         "col_prec": prec, "lpoly": [_lpoly_ints(lp[i]) for i in range(count)], "stats": stats,
     }
+
+
+def cr_policy_cost(fam, p, coeffs):
+    """Host-only plan of one hypersurface under fam.policy: the cr_stats counters."""
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32))
+    stats = cr_stats()
+    _check(lib().cr_policy_cost(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), ctypes.byref(stats)))
+    return stats
 
 
 def cr_release():

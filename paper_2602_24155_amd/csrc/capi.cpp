@@ -15,12 +15,15 @@
 
 #include "device_layout.hpp"
 #include "host.hpp"
+#include "plan.hpp"
 
 namespace crf {
 size_t reduce_lds_bytes(const DevFamily &fam, int ct);
 hipError_t launch_reduce(const DevFamily &fam, const DevItem *items, const DevTile *tiles, int ntiles,
-                         const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int ct,
-                         int *err, hipStream_t stream);
+                         const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                         uint64_t *store, uint64_t *hbuf, int ct, int *err, hipStream_t stream);
+hipError_t launch_combine(const DevItem *items, const DevComb *comb, int ncomb, const int32_t *msrc,
+                          const uint64_t *malpha, uint64_t *store, int s, hipStream_t stream);
 hipError_t launch_assemble(const DevFamily &fam, const DevItem *items, int nitems, const uint64_t *hbuf,
                            hipStream_t stream);
 bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb);
@@ -29,8 +32,9 @@ hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, c
                               int D, hipStream_t stream);
 bool mfma_supports_digits(int D);
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
-                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
-                               const uint32_t *slots, int *err, int D, bool z32, hipStream_t stream);
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
+                               hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
 }  // namespace crf
 
@@ -55,18 +59,18 @@ struct Arena {
     size_t host_cap = 0;
     bool ensure(size_t dbytes, size_t hbytes) {
         if (dbytes > dev_cap) {
+            const size_t cap = std::max(dbytes, dev_cap + dev_cap / 2);
             if (dev) (void)hipFree(dev);
             dev = nullptr;
             dev_cap = 0;
-            size_t cap = std::max(dbytes, dev_cap * 2);
             if (hipMalloc(&dev, cap) != hipSuccess) return false;
             dev_cap = cap;
         }
         if (hbytes > host_cap) {
+            const size_t cap = std::max(hbytes, host_cap + host_cap / 2);
             if (host) (void)hipHostFree(host);
             host = nullptr;
             host_cap = 0;
-            size_t cap = std::max(hbytes, host_cap * 2);
             if (hipHostMalloc(&host, cap, hipHostMallocDefault) != hipSuccess) return false;
             host_cap = cap;
         }
@@ -171,8 +175,12 @@ bool check_family(const cr_family *fam, std::string &err) {
         err = "unknown engine";
         return false;
     }
-    if (fam->policy != CR_POLICY_DEPTH_FIRST) {
+    if (fam->policy < CR_POLICY_DEPTH_FIRST || fam->policy > CR_POLICY_LEARNED) {
         err = "unknown policy";
+        return false;
+    }
+    if (fam->policy != CR_POLICY_DEPTH_FIRST && fam->engine == 2) {
+        err = "engine 2 (LDS-gather MFMA kernel) runs the depth-first policy only";
         return false;
     }
     return true;
@@ -239,6 +247,35 @@ cr_status cr_check_smooth(const cr_family *fam, int32_t p, const uint32_t *coeff
     return CR_OK;
 }
 
+cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs, cr_stats *stats) {
+    std::string err;
+    if (!check_family(fam, err) || !coeffs || !stats) return fail(CR_EINVAL, err.empty() ? "null pointer" : err);
+    FamilyEntry *fe;
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        fe = get_family(fam, err);
+    }
+    if (!fe) return fail(CR_EINVAL, err);
+    auto t0 = std::chrono::steady_clock::now();
+    ItemSetup it;
+    cr_status st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err);
+    if (st != CR_OK) return fail(st, err);
+    ItemPlan plan;
+    if (!plan_item(fe->fam, it, fam->policy, plan, err, nullptr)) return fail(CR_EINVAL, err);
+    std::memset(stats, 0, sizeof(*stats));
+    stats->start_blocks = it.nchain();
+    stats->column_steps = plan.column_steps;
+    stats->chunks = plan.chunks;
+    stats->vectors = plan.vectors;
+    stats->merged_terms = plan.merged_terms;
+    stats->combined_groups = plan.combined_groups;
+    stats->phases = (int32_t)plan.phase.size();
+    stats->policy = fam->policy;
+    stats->engine = -1;
+    stats->setup_ms = ms_since(t0);
+    return CR_OK;
+}
+
 cr_status cr_release(void) {
     std::lock_guard<std::mutex> lk(g_mutex);
     g_arena.release();
@@ -262,7 +299,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     auto t0 = std::chrono::steady_clock::now();
 
-    // ---- host setup, one item per task
+    // ---- host setup and reduction plan, one item per task
     DevFamily df{};
     df.nv = F.nv;
     df.n = F.n;
@@ -274,21 +311,25 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     df.F = F.fin.count;
     df.ndir = F.dirs.count;
     df.nfinU = F.finU.count;
+    const int policy = fam->policy;
     int nrt = 0, nkb = 0;
     const bool want_mfma = (fam->engine == 0 || fam->engine == 2) && mfma_shape(df, nrt, nkb);
     // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
     const bool use_bins = fam->engine == 0 && fe->bl_ok;
     std::vector<ItemSetup> items(count);
+    std::vector<ItemPlan> plans(count);
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
     std::vector<DigitParams> dps(count);
     std::vector<char> digit_ok(count, 0);
+    const DirChooser *chooser = nullptr;
     parallel_for(count, [&](int i) {
         st[i] = setup_item(F, primes[i], coeffs + (size_t)i * nco, fam->r, fam->n_series, items[i], errs[i]);
         if (st[i] == CR_OK && items[i].b != b) {
             st[i] = CR_ESELFCHECK;
             errs[i] = "basis size differs from the Hodge numbers";
         }
+        if (st[i] == CR_OK && !plan_item(F, items[i], policy, plans[i], errs[i], chooser)) st[i] = CR_EINVAL;
         if (st[i] == CR_OK && want_mfma) {
             ItemSetup &it = items[i];
             int umax = 0;
@@ -303,7 +344,6 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     });
     const double setup_ms = ms_since(t0);
 
-    // ---- pack device buffers
     std::vector<int> live;
     for (int i = 0; i < count; i++)
         if (st[i] == CR_OK) live.push_back(i);
@@ -320,48 +360,75 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
             stats->setup_ms = setup_ms;
+            stats->policy = policy;
         }
         return first;
     }
-    size_t nchain = 0, psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
-    for (int i : live) nchain += items[i].nchain();
     bool use_mfma = want_mfma;
     for (int li = 0; li < nlive && use_mfma; li++) use_mfma = digit_ok[live[li]] != 0;
     for (int li = 0; li < nlive && use_mfma && use_bins; li++)
         if (!mfma4_supports(df, dps[live[li]].D)) use_mfma = false;  // packed for the other layout: fall back
+    if (use_mfma && !use_bins && policy != CR_POLICY_DEPTH_FIRST) use_mfma = false;
     int ct = 32;
     if (!use_mfma) {
         while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
         if (reduce_lds_bytes(df, ct) > 64 * 1024) return fail(CR_EINVAL, "family too large for the LDS tile");
     }
-    // tiles of ct chains of one item; for the MFMA kernel grouped by digit count D
+
+    // ---- vectors of every phase in launch order (phase, digit group, item), tiles of ct vectors of one item
+    std::vector<int> gkey(nlive, 0), dvals;
+    for (int li = 0; li < nlive; li++)
+        if (use_mfma) gkey[li] = dps[live[li]].D + 100 * dps[live[li]].z32;
+    dvals = gkey;
+    std::sort(dvals.begin(), dvals.end());
+    dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
+    int nphase = 0;
+    for (int i : live) nphase = std::max(nphase, (int)plans[i].phase.size());
+    struct Launch {
+        int phase, key, tile0, ntiles;
+    };
+    std::vector<Launch> launches;
     std::vector<DevTile> tiles;
-    std::vector<std::pair<int, std::pair<int, int>>> groups;  // (D + 100 z32, (first tile, count))
-    std::vector<int> dvals;
-    if (use_mfma) {
-        for (int li = 0; li < nlive; li++) dvals.push_back(dps[live[li]].D + 100 * dps[live[li]].z32);
-        std::sort(dvals.begin(), dvals.end());
-        dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
-    } else {
-        dvals.push_back(0);
-    }
-    for (int D : dvals) {
-        const int first = (int)tiles.size();
-        for (int li = 0; li < nlive; li++) {
-            if (use_mfma && dps[live[li]].D + 100 * dps[live[li]].z32 != D) continue;
-            const ItemSetup &it = items[live[li]];
-            for (int c0 = 0; c0 < it.nchain(); c0 += ct) {
-                DevTile t{};
-                t.item = li;
-                t.count = std::min(ct, it.nchain() - c0);
-                t.chain0 = c0;  // item-relative for now
-                t.steps = it.chain_pole[c0] - F.n;
-                tiles.push_back(t);
+    std::vector<std::vector<size_t>> vec0(nlive, std::vector<size_t>(nphase, 0));
+    size_t nvec = 0;
+    for (int t = 0; t < nphase; t++)
+        for (int key : dvals) {
+            const int first = (int)tiles.size();
+            for (int li = 0; li < nlive; li++) {
+                const ItemPlan &pl = plans[live[li]];
+                if (gkey[li] != key || t >= (int)pl.phase.size()) continue;
+                const auto &ph = pl.phase[t];
+                vec0[li][t] = nvec;
+                for (int c0 = 0; c0 < (int)ph.size(); c0 += ct) {
+                    DevTile tl{};
+                    tl.item = li;
+                    tl.count = std::min(ct, (int)ph.size() - c0);
+                    tl.chain0 = (int32_t)(nvec + c0);
+                    tl.steps = ph[c0].pole - ph[c0].pend;
+                    tiles.push_back(tl);
+                }
+                nvec += ph.size();
             }
+            if ((int)tiles.size() > first) launches.push_back({t, key, first, (int)tiles.size() - first});
         }
-        groups.push_back({D, {first, (int)tiles.size() - first}});
+    std::vector<int32_t> row0(nlive, 0);
+    size_t nrows = 0, ncomb = 0, nmem = 0, nfin_all = 0, ncoef = 0;
+    for (int li = 0; li < nlive; li++) {
+        const ItemPlan &pl = plans[live[li]];
+        row0[li] = (int32_t)nrows;
+        nrows += pl.nrows;
+        for (auto &cb : pl.comb) ncomb += cb.size();
+        nmem += pl.msrc.size();
+        for (auto &ph : pl.phase)
+            for (auto &v : ph) nfin_all += v.out < 0;
+        ncoef += (size_t)(items[live[li]].nchain() + b) * b;
     }
-    // device layout
+    if (nvec >= (size_t)INT32_MAX || nrows >= (size_t)INT32_MAX / 2)
+        return fail(CR_ENOMEM, "batch too large for 32-bit vector indices");
+
+    // ---- device layout
+    const size_t psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
+    const int sdim = F.g.count;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -379,17 +446,25 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         for (int li = 0; li < nlive; li++) apack_off[li] = take(items[live[li]].apack.size());
     }
     const size_t o_rho = take(8 * rho_len * nlive);
-    const size_t o_coef = take(8 * (size_t)b * nchain);
-    const size_t o_cu = take(2 * (size_t)F.nv * nchain);
-    const size_t o_cg = take(4 * nchain);
-    const size_t o_cp = take(4 * nchain);
+    const size_t o_coef = take(8 * ncoef);
+    const size_t o_cu = take(2 * (size_t)F.nv * nvec);
+    const size_t o_cg = take(4 * nvec);
+    const size_t o_cp = take(4 * nvec);
+    const size_t o_vx = take(sizeof(DevVec) * nvec);
+    const size_t o_comb = take(sizeof(DevComb) * std::max<size_t>(ncomb, 1));
+    const size_t o_msrc = take(4 * std::max<size_t>(nmem, 1));
+    const size_t o_malpha = take(8 * std::max<size_t>(nmem, 1));
+    const size_t o_fvec = take(4 * std::max<size_t>(nfin_all, 1));
+    const size_t o_frow = take(4 * std::max<size_t>(nfin_all, 1));
     const size_t o_err = take(4);
     const size_t h_end = off;  // everything above is uploaded
     const size_t o_Y = take(8 * (size_t)b * b * nlive);
     const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
-    const size_t o_hbuf = take(8 * (size_t)F.fin.count * nchain);
+    const size_t o_hbuf = take(8 * (size_t)F.fin.count * nvec);
+    const size_t o_store = take(8 * (size_t)sdim * std::max<size_t>(nrows, 1));
     const size_t d_end = off;
-    if (!g_arena.ensure(d_end, d_end)) return fail(CR_ENOMEM, "device or pinned host allocation failed");
+    if (!g_arena.ensure(d_end, h_end + 8 * (size_t)b * b * nlive + 256))
+        return fail(CR_ENOMEM, "device or pinned host allocation failed");
     unsigned char *hb = static_cast<unsigned char *>(g_arena.host);
     unsigned char *db = static_cast<unsigned char *>(g_arena.dev);
     std::memcpy(hb + o_tables, fe->tables.data(), fe->tables.size());
@@ -400,22 +475,87 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     df.dirs = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_dirs);
     df.finU = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_finU);
     DevItem *hitems = reinterpret_cast<DevItem *>(hb + o_items);
-    size_t chain_at = 0;
-    std::vector<size_t> item_chain0(nlive);
+    int16_t *hcu = reinterpret_cast<int16_t *>(hb + o_cu);
+    int32_t *hcg = reinterpret_cast<int32_t *>(hb + o_cg);
+    int32_t *hcp = reinterpret_cast<int32_t *>(hb + o_cp);
+    DevVec *hvx = reinterpret_cast<DevVec *>(hb + o_vx);
+    DevComb *hcomb = reinterpret_cast<DevComb *>(hb + o_comb);
+    int32_t *hmsrc = reinterpret_cast<int32_t *>(hb + o_msrc);
+    uint64_t *hmal = reinterpret_cast<uint64_t *>(hb + o_malpha);
+    int32_t *hfvec = reinterpret_cast<int32_t *>(hb + o_fvec);
+    int32_t *hfrow = reinterpret_cast<int32_t *>(hb + o_frow);
+    // combine entries grouped by the phase that reads them
+    std::vector<size_t> comb_first(nphase + 1, 0), comb_count(nphase + 1, 0);
+    {
+        size_t at = 0, mat = 0;
+        for (int t = 1; t < nphase; t++) {
+            comb_first[t] = at;
+            for (int li = 0; li < nlive; li++) {
+                const ItemPlan &pl = plans[live[li]];
+                if (t >= (int)pl.comb.size()) continue;
+                for (const PlanComb &pc : pl.comb[t]) {
+                    DevComb &dc = hcomb[at++];
+                    dc.row = row0[li] + pc.row;
+                    dc.item = li;
+                    dc.m0 = (int32_t)mat;
+                    for (int j = pc.m0; j < pc.m1; j++) {
+                        const int32_t src = pl.msrc[j];
+                        hmsrc[mat] = src >= 0 ? row0[li] + src : src;
+                        hmal[mat] = pl.malpha[j];
+                        mat++;
+                    }
+                    dc.m1 = (int32_t)mat;
+                }
+            }
+            comb_count[t] = at - comb_first[t];
+        }
+    }
+    size_t coef_at = 0, fin_at = 0;
     for (int li = 0; li < nlive; li++) {
         const ItemSetup &it = items[live[li]];
+        const ItemPlan &pl = plans[live[li]];
         DevItem &di = hitems[li];
+        std::memset(&di, 0, sizeof(di));
         di.q = it.mq.q;
         di.mu = it.mq.mu;
         di.sbits = it.mq.sbits;
         di.b = b;
-        di.chain0 = (int32_t)chain_at;
         di.nchain = it.nchain();
         di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
         di.rho = reinterpret_cast<const uint64_t *>(db + o_rho) + rho_len * li;
-        di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + (size_t)b * chain_at;
+        di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + coef_at;
         di.Y = reinterpret_cast<uint64_t *>(db + o_Y) + (size_t)b * b * li;
         di.H = reinterpret_cast<uint64_t *>(db + o_H) + (size_t)F.fin.count * b * li;
+        uint64_t *hc = reinterpret_cast<uint64_t *>(hb + o_coef) + coef_at;
+        std::memcpy(hc, it.coef.data(), 8 * it.coef.size());
+        std::memset(hc + it.coef.size(), 0, 8 * (size_t)b * b);
+        for (int c = 0; c < b; c++) hc[it.coef.size() + (size_t)c * b + c] = 1;
+        coef_at += (size_t)(it.nchain() + b) * b;
+        // vectors
+        di.fvec = reinterpret_cast<const int32_t *>(db + o_fvec) + fin_at;
+        di.frow = reinterpret_cast<const int32_t *>(db + o_frow) + fin_at;
+        int nfin = 0;
+        for (int t = 0; t < (int)pl.phase.size(); t++) {
+            const auto &ph = pl.phase[t];
+            for (size_t k = 0; k < ph.size(); k++) {
+                const PlanVec &pv = ph[k];
+                const size_t g = vec0[li][t] + k;
+                for (int i = 0; i < F.nv; i++) hcu[g * F.nv + i] = pv.u[i];
+                hcg[g] = pv.gamma;
+                hcp[g] = pv.pole;
+                hvx[g].pend = pv.pend;
+                hvx[g].in = pv.in >= 0 ? row0[li] + pv.in : -1;
+                hvx[g].out = pv.out >= 0 ? row0[li] + pv.out : -1;
+                hvx[g].dir = pv.dir;
+                if (pv.out < 0) {
+                    hfvec[fin_at + nfin] = (int32_t)g;
+                    hfrow[fin_at + nfin] = pv.crow;
+                    nfin++;
+                }
+            }
+        }
+        di.nfin = nfin;
+        fin_at += nfin;
         if (use_mfma) {
             const DigitParams &dp = dps[live[li]];
             DevDigitItem &dd = reinterpret_cast<DevDigitItem *>(hb + o_ditems)[li];
@@ -438,7 +578,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             dd.h = dp.h;
             dd.ds = dp.ds;
             dd.z32 = dp.z32;
-            dd.chain0 = (int32_t)chain_at;
+            dd.chain0 = 0;
             dd.nchain = it.nchain();
             dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
             std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
@@ -446,67 +586,76 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
         }
         std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
-        std::memcpy(hb + o_coef + 8 * (size_t)b * chain_at, it.coef.data(), 8 * it.coef.size());
-        std::memcpy(hb + o_cu + 2 * (size_t)F.nv * chain_at, it.chain_u.data(), 2 * it.chain_u.size());
-        std::memcpy(hb + o_cg + 4 * chain_at, it.chain_g.data(), 4 * it.chain_g.size());
-        std::memcpy(hb + o_cp + 4 * chain_at, it.chain_pole.data(), 4 * it.chain_pole.size());
-        item_chain0[li] = chain_at;
-        chain_at += it.nchain();
     }
-    DevTile *htiles = reinterpret_cast<DevTile *>(hb + o_tiles);
-    for (size_t k = 0; k < tiles.size(); k++) {
-        htiles[k] = tiles[k];
-        htiles[k].chain0 += (int32_t)item_chain0[tiles[k].item];
-    }
+    std::memcpy(hb + o_tiles, tiles.data(), sizeof(DevTile) * tiles.size());
     std::memset(hb + o_err, 0, 4);
 
-    auto t1 = std::chrono::steady_clock::now();
+    // ---- device work: per phase the combines it reads, then its reductions; then the assembly
     hipEvent_t e0, e1, em;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventCreate(&em);
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
     hipError_t he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, stream);
     (void)hipEventRecord(e0, stream);
-    if (he == hipSuccess && use_mfma) {
-        for (auto &g : groups) {
-            if (he != hipSuccess) break;
-            const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + o_ditems);
-            const DevTile *gt = reinterpret_cast<const DevTile *>(db + o_tiles) + g.second.first;
-            const int16_t *cu = reinterpret_cast<const int16_t *>(db + o_cu);
-            const int32_t *cgp = reinterpret_cast<const int32_t *>(db + o_cg);
-            const int32_t *cp = reinterpret_cast<const int32_t *>(db + o_cp);
-            uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + o_hbuf);
-            int *errp = reinterpret_cast<int *>(db + o_err);
-            const int Dg = g.first % 100;
-            const bool z32g = g.first >= 100;
-            if (use_bins)
-                he = launch_reduce_mfma4(df, ditems, gt, g.second.second, cu, cgp, cp, hb64,
-                                         reinterpret_cast<const uint32_t *>(db + o_tables + fe->off_slots), errp,
-                                         Dg, z32g, stream);
-            else
-                he = launch_reduce_mfma(df, ditems, gt, g.second.second, cu, cgp, cp, hb64, errp, Dg, stream);
+    const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + o_items);
+    const int16_t *cu = reinterpret_cast<const int16_t *>(db + o_cu);
+    const int32_t *cgp = reinterpret_cast<const int32_t *>(db + o_cg);
+    const int32_t *cp = reinterpret_cast<const int32_t *>(db + o_cp);
+    const DevVec *vxp = reinterpret_cast<const DevVec *>(db + o_vx);
+    uint64_t *storep = reinterpret_cast<uint64_t *>(db + o_store);
+    uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + o_hbuf);
+    int *errp = reinterpret_cast<int *>(db + o_err);
+    for (int t = 0; t < nphase && he == hipSuccess; t++) {
+        if (t > 0 && comb_count[t] > 0) {
+            hipEvent_t a, z;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&z);
+            (void)hipEventRecord(a, stream);
+            he = launch_combine(ditems_v, reinterpret_cast<const DevComb *>(db + o_comb) + comb_first[t],
+                                (int)comb_count[t], reinterpret_cast<const int32_t *>(db + o_msrc),
+                                reinterpret_cast<const uint64_t *>(db + o_malpha), storep, sdim, stream);
+            (void)hipEventRecord(z, stream);
+            cev.push_back({a, z});
+        }
+        for (const Launch &L : launches) {
+            if (L.phase != t || he != hipSuccess) continue;
+            const DevTile *gt = reinterpret_cast<const DevTile *>(db + o_tiles) + L.tile0;
+            if (use_mfma) {
+                const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + o_ditems);
+                const int Dg = L.key % 100;
+                const bool z32g = L.key >= 100;
+                if (use_bins)
+                    he = launch_reduce_mfma4(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
+                                             reinterpret_cast<const uint32_t *>(db + o_tables + fe->off_slots), errp,
+                                             Dg, z32g, stream);
+                else
+                    he = launch_reduce_mfma(df, ditems, gt, L.ntiles, cu, cgp, cp, hb64, errp, Dg, stream);
+            } else {
+                he = launch_reduce(df, ditems_v, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64, ct, errp, stream);
+            }
         }
     }
-    else if (he == hipSuccess)
-        he = launch_reduce(df, reinterpret_cast<const DevItem *>(db + o_items),
-                           reinterpret_cast<const DevTile *>(db + o_tiles), (int)tiles.size(),
-                           reinterpret_cast<const int16_t *>(db + o_cu), reinterpret_cast<const int32_t *>(db + o_cg),
-                           reinterpret_cast<const int32_t *>(db + o_cp),
-                           reinterpret_cast<uint64_t *>(db + o_hbuf), ct,
-                           reinterpret_cast<int *>(db + o_err), stream);
     (void)hipEventRecord(em, stream);
-    if (he == hipSuccess)
-        he = launch_assemble(df, reinterpret_cast<const DevItem *>(db + o_items), nlive,
-                             reinterpret_cast<const uint64_t *>(db + o_hbuf), stream);
+    if (he == hipSuccess) he = launch_assemble(df, ditems_v, nlive, hb64, stream);
     (void)hipEventRecord(e1, stream);
     if (he == hipSuccess) he = hipMemcpyAsync(hb + o_Y, db + o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipMemcpyAsync(hb + o_err, db + o_err, 4, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
-    float dev_ms = 0, red_ms = 0, asm_ms = 0;
+    float dev_ms = 0, red_ms = 0, asm_ms = 0, comb_ms = 0;
     if (he == hipSuccess) {
         (void)hipEventElapsedTime(&dev_ms, e0, e1);
         (void)hipEventElapsedTime(&red_ms, e0, em);
         (void)hipEventElapsedTime(&asm_ms, em, e1);
+        for (auto &ce : cev) {
+            float x = 0;
+            (void)hipEventElapsedTime(&x, ce.first, ce.second);
+            comb_ms += x;
+        }
+    }
+    for (auto &ce : cev) {
+        (void)hipEventDestroy(ce.first);
+        (void)hipEventDestroy(ce.second);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -515,7 +664,6 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     int derr;
     std::memcpy(&derr, hb + o_err, 4);
     if (derr) return fail(CR_ESELFCHECK, "device reduction invariant violated (code " + std::to_string(derr) + ")");
-    (void)t1;
 
     // ---- finish: unscale, Q(T)
     auto t2 = std::chrono::steady_clock::now();
@@ -540,13 +688,19 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         std::memset(stats, 0, sizeof(*stats));
         for (int i : live) {
             stats->start_blocks += items[i].nchain();
-            stats->column_steps += items[i].column_steps;
-            stats->chunks += items[i].chunks;
+            stats->column_steps += plans[i].column_steps;
+            stats->chunks += plans[i].chunks;
+            stats->vectors += plans[i].vectors;
+            stats->merged_terms += plans[i].merged_terms;
+            stats->combined_groups += plans[i].combined_groups;
         }
         stats->setup_ms = setup_ms;
         stats->device_ms = dev_ms;
-        stats->reduce_ms = red_ms;
+        stats->reduce_ms = red_ms - comb_ms;
+        stats->combine_ms = comb_ms;
         stats->engine = use_mfma ? (use_bins ? 0 : 2) : 1;
+        stats->policy = policy;
+        stats->phases = nphase;
         stats->assemble_ms = asm_ms;
         stats->finish_ms = finish_ms;
     }

@@ -30,11 +30,29 @@ struct DevItem {
     int32_t b;       // side of Phi'
     int32_t chain0;  // first chain (global index)
     int32_t nchain;
+    int32_t nfin;    // vectors that reach pole n
+    int32_t pad_;
     const uint64_t *psi;   // nsrc x T right inverse of J_S
     const uint64_t *rho;   // b x F Griffiths-Dwork coordinate map
-    const uint64_t *coef;  // nchain x b start coefficients
+    const uint64_t *coef;  // (nchain + b) x b: start coefficients, then the unit rows e_c
+    const int32_t *fvec;   // nfin: global index of each vector that reaches pole n
+    const int32_t *frow;   // nfin: its coefficient row in coef
     uint64_t *Y;           // b x b output (coordinates, mod q)
     uint64_t *H;           // F x b scratch: summed pole-n numerators
+};
+
+// Per reduced vector (one entry per vector of every phase of a plan).
+struct DevVec {
+    int32_t pend;  // pole at which the vector stops
+    int32_t in;    // store row holding the start vector, or -1: the unit vector e_gamma
+    int32_t out;   // store row receiving the result, or -1: pole-n numerators (hbuf row)
+    int32_t dir;   // direction forced for the whole range, or -1: Algorithm 3 chunks
+};
+
+// A store row built between two phases: row = sum_{m0 <= j < m1} alpha_j src_j
+// (src_j >= 0 a store row, src_j < 0 the unit vector e_{-src_j - 1}).
+struct DevComb {
+    int32_t row, item, m0, m1;
 };
 
 // A tile of chains of one item processed by one workgroup.

@@ -12,7 +12,14 @@
 // 4.2); inside a chunk the matrices M(y) = R_{x + y v, v} are applied from
 // y = k-1 down to 0 as in Algorithm 2, with M(y) never materialised.
 //
-// k_assemble: H = sum_chains coef (x) h_chain and Y = rho H (Section 3.3 step (2)).
+// A chain is one vector of a reduction plan: it may start from a stored
+// residue vector instead of e_gamma, stop at a combine point (pole pend > n)
+// and leave its result in a store row, and may have one direction forced for
+// its whole range (the learned policy).
+//
+// k_combine: store rows built between phases (like terms combined, Section 3.4).
+// k_assemble: H = sum coef (x) h over the vectors that reach pole n, and
+// Y = rho H (Section 3.3 step (2)).
 #include <hip/hip_runtime.h>
 
 #include "device_layout.hpp"
@@ -80,6 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
                                                             const int16_t *__restrict__ cu,
                                                             const int32_t *__restrict__ cg,
                                                             const int32_t *__restrict__ cpole,
+                                                            const DevVec *__restrict__ vx,
+                                                            u64 *__restrict__ store,
                                                             u64 *__restrict__ hbuf, int ct,
                                                             int *__restrict__ err) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -94,6 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
     int *dir = V + ct * 8;
     int *kleft = dir + ct;
     int *pole = kleft + ct;
+    int *pend = pole + ct;
     const int tid = threadIdx.x;
     const int nch = tile.count;
 
@@ -101,22 +111,34 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
     __syncthreads();
     if (tid < nch) {
         const int g = tile.chain0 + tid;
+        const DevVec x = vx[g];
         for (int i = 0; i < nv; i++) U[tid * 8 + i] = cu[(size_t)g * nv + i];
         pole[tid] = cpole[g];
+        pend[tid] = x.pend;
         kleft[tid] = 0;
-        w[tid * s + cg[g]] = 1;
+        if (x.dir >= 0) {  // one forced direction for the whole range
+            for (int i = 0; i < nv; i++) V[tid * 8 + i] = fam.dirs[x.dir * nv + i];
+            dir[tid] = x.dir;
+            kleft[tid] = pole[tid] - x.pend;
+        }
+        if (x.in < 0) w[tid * s + cg[g]] = 1;
+    }
+    for (int idx = tid; idx < nch * s; idx += kThreads) {
+        const int c = idx / s, r = idx - c * s;
+        const int in = vx[tile.chain0 + c].in;
+        if (in >= 0) w[idx] = store[(size_t)in * s + r];
     }
     __syncthreads();
 
     for (int step = 0; step < tile.steps; step++) {
-        if (tid < nch && pole[tid] > fam.n && kleft[tid] == 0) {
+        if (tid < nch && pole[tid] > pend[tid] && kleft[tid] == 0) {
             int d0, k0;
-            choose_chunk(fam, &U[tid * 8], pole[tid] - fam.n, &V[tid * 8], d0, k0);
+            choose_chunk(fam, &U[tid * 8], pole[tid] - pend[tid], &V[tid * 8], d0, k0);
             if (d0 < 0 || k0 < 1) {  // no valid direction: cannot happen for d >= |S|
                 atomicOr(err, 1);
                 d0 = 0;
                 k0 = 1 << 30;
-                pole[tid] = fam.n;
+                pole[tid] = pend[tid];
             }
             dir[tid] = d0;
             kleft[tid] = k0;
@@ -125,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
         // t = psi[:, cols(v)] w
         for (int idx = tid; idx < nch * nsrc; idx += kThreads) {
             const int c = idx / nsrc, mu = idx - c * nsrc;
-            if (pole[c] <= fam.n) continue;
+            if (pole[c] <= pend[c]) continue;
             const int16_t *cm = fam.colmap + (size_t)dir[c] * s;
             const u64 *prow = it.psi + (size_t)mu * T;
             const u64 *wc = w + (size_t)c * s;
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
         // w'[r] = sum_i (u_i + r_i + [i not in S]) t[src(r, i)],  u = U - v
         for (int idx = tid; idx < nch * s; idx += kThreads) {
             const int c = idx / s, r = idx - c * s;
-            if (pole[c] <= fam.n) continue;
+            if (pole[c] <= pend[c]) continue;
             u128 acc = 0;
             for (int i = 0; i < nv; i++) {
                 const int src = fam.gsrc[r * nv + i];
@@ -156,21 +178,29 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
             w[(size_t)c * s + r] = md.reduce(acc);
         }
         __syncthreads();
-        if (tid < nch && pole[tid] > fam.n) {
+        if (tid < nch && pole[tid] > pend[tid]) {
             for (int i = 0; i < nv; i++) U[tid * 8 + i] -= V[tid * 8 + i];
             pole[tid]--;
             kleft[tid]--;
         }
         __syncthreads();
     }
+    // combine point: the vector goes to its store row
+    for (int idx = tid; idx < nch * s; idx += kThreads) {
+        const int c = idx / s, r = idx - c * s;
+        const int out = vx[tile.chain0 + c].out;
+        if (out >= 0) store[(size_t)out * s + r] = w[idx];
+    }
     // pole n: numerator x^U g / x^S written into fin space
     for (int c = 0; c < nch; c++) {
+        if (vx[tile.chain0 + c].out >= 0) continue;
         u64 *h = hbuf + (size_t)(tile.chain0 + c) * fam.F;
         for (int f = tid; f < fam.F; f += kThreads) h[f] = 0;
     }
     __syncthreads();
     for (int idx = tid; idx < nch * s; idx += kThreads) {
         const int c = idx / s, k = idx - c * s;
+        if (vx[tile.chain0 + c].out >= 0) continue;
         int Ui = -1;
         for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
             bool eq = true;
@@ -185,7 +215,27 @@ __global__ __launch_bounds__(kThreads) void k_reduce_chains(DevFamily fam, const
     }
 }
 
-// One workgroup per item: H = sum_k h_k (x) coef_k, then Y = rho H.
+// Store rows built between two phases: row = sum_j alpha_j src_j (mod q).
+__global__ __launch_bounds__(64) void k_combine(const DevItem *__restrict__ items, const DevComb *__restrict__ comb,
+                                                const int32_t *__restrict__ msrc, const u64 *__restrict__ malpha,
+                                                u64 *__restrict__ store, int s) {
+    const DevComb cb = comb[blockIdx.x];
+    const DevItem it = items[cb.item];
+    const DMod md{it.q, it.mu, it.sbits};
+    for (int r = threadIdx.x; r < s; r += 64) {
+        u128 acc = 0;
+        for (int j = cb.m0; j < cb.m1; j++) {
+            const int src = msrc[j];
+            const u64 x = src >= 0 ? store[(size_t)src * s + r] : (u64)(r == -src - 1);
+            acc += (u128)malpha[j] * x;
+            if (((j - cb.m0) & 127) == 127) acc = md.reduce(acc);
+        }
+        store[(size_t)cb.row * s + r] = md.reduce(acc);
+    }
+}
+
+// One workgroup per item: H = sum_k h_k (x) coef_k over the vectors that reach
+// pole n, then Y = rho H.
 __global__ __launch_bounds__(kThreads) void k_assemble(DevFamily fam, const DevItem *__restrict__ items,
                                                        const u64 *__restrict__ hbuf) {
     const DevItem it = items[blockIdx.x];
@@ -194,8 +244,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevFamily fam, const DevI
     for (int idx = threadIdx.x; idx < F * b; idx += kThreads) {
         const int f = idx / b, c = idx - f * b;
         u128 acc = 0;
-        for (int k = 0; k < it.nchain; k++) {
-            acc += (u128)hbuf[(size_t)(it.chain0 + k) * F + f] * it.coef[(size_t)k * b + c];
+        for (int k = 0; k < it.nfin; k++) {
+            acc += (u128)hbuf[(size_t)it.fvec[k] * F + f] * it.coef[(size_t)it.frow[k] * b + c];
             if ((k & 127) == 127) acc = md.reduce(acc);
         }
         it.H[idx] = md.reduce(acc);
@@ -213,16 +263,23 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevFamily fam, const DevI
 }
 
 size_t reduce_lds_bytes(const DevFamily &fam, int ct) {
-    return (size_t)ct * (fam.s + fam.nsrc) * 8 + (size_t)ct * (8 + 8 + 3) * 4;
+    return (size_t)ct * (fam.s + fam.nsrc) * 8 + (size_t)ct * (8 + 8 + 4) * 4;
 }
 
 hipError_t launch_reduce(const DevFamily &fam, const DevItem *items, const DevTile *tiles, int ntiles,
-                         const int16_t *cu, const int32_t *cg, const int32_t *cpole, u64 *hbuf, int ct,
-                         int *err, hipStream_t stream) {
+                         const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx, u64 *store,
+                         u64 *hbuf, int ct, int *err, hipStream_t stream) {
     if (ntiles == 0) return hipSuccess;
     size_t lds = reduce_lds_bytes(fam, ct);
     hipLaunchKernelGGL(k_reduce_chains, dim3(ntiles), dim3(kThreads), lds, stream, fam, items, tiles, cu, cg, cpole,
-                       hbuf, ct, err);
+                       vx, store, hbuf, ct, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const DevItem *items, const DevComb *comb, int ncomb, const int32_t *msrc,
+                          const u64 *malpha, u64 *store, int s, hipStream_t stream) {
+    if (ncomb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine, dim3(ncomb), dim3(64), 0, stream, items, comb, msrc, malpha, store, s);
     return hipGetLastError();
 }
 

@@ -352,19 +352,53 @@ __device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, co
     }
 }
 
+// Balanced base-B digits of x (0 <= x < Q') written to the D digit planes at xp
+// (plane stride kCT * XS bytes).  x + bias is cut at B^DS so that both halves
+// stay below 2^24 for the 32-bit magic division by B.
+template <int D, int XS>
+__device__ __forceinline__ static void put_digits(int8_t *xp, double x, double Qd, double bias, double Bsplit,
+                                                  double invBsplit, uint32_t magic, int shift, int Bi, int halfB) {
+    constexpr int DS = (D + 1) / 2;
+    double xs = x + bias;
+    if (xs >= Qd) xs -= Qd;
+    double xh = floor(xs * invBsplit);
+    double rl = fma(-xh, Bsplit, xs);
+    if (rl < 0.0) {
+        rl += Bsplit;
+        xh -= 1.0;
+    } else if (rl >= Bsplit) {
+        rl -= Bsplit;
+        xh += 1.0;
+    }
+    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
+#pragma unroll
+    for (int jd = 0; jd < DS; jd++) {
+        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
+        xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
+        vl = qd;
+    }
+#pragma unroll
+    for (int jd = DS; jd < D; jd++) {
+        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
+        xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
+        vh = qd;
+    }
+}
+
 template <int NRT, int NKB, int D, int NV, bool Z32>
 __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const DevDigitItem *__restrict__ items,
                                                            const DevTile *__restrict__ tiles,
                                                            const int16_t *__restrict__ cu,
                                                            const int32_t *__restrict__ cg,
                                                            const int32_t *__restrict__ cpole,
+                                                           const DevVec *__restrict__ vx,
+                                                           uint64_t *__restrict__ store,
                                                            uint64_t *__restrict__ hbuf,
                                                            const uint32_t *__restrict__ slots, int *__restrict__ err) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
     constexpr int NT = 64 * NRT;
     constexpr int XB = D * kCT * XS;  // bytes of one set of digit planes
-    constexpr int DS = (D + 1) / 2;
     __shared__ __align__(16) int8_t Xbuf[2 * XB];
     __shared__ int16_t colmapL[kTabCap];
     __shared__ int8_t dirsL[512];
@@ -388,33 +422,11 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
     for (int idx = tid; idx < fam.ndir * s; idx += NT) colmapL[idx] = fam.colmap[idx];
     for (int idx = tid; idx < fam.ndir * nv; idx += NT) dirsL[idx] = fam.dirs[idx];
     for (int idx = tid; idx < 2 * XB / 16; idx += NT) reinterpret_cast<v4i *>(Xbuf)[idx] = v4i{0, 0, 0, 0};
-    for (int idx = tid; idx < nch * F; idx += NT) hbuf[(size_t)tile.chain0 * F + idx] = 0;
-    __syncthreads();
-
-    // chain state (registers; identical in every lane of chain c)
-    int U[8], V[8], dir = 0, kleft = 0, pole = n;
-#pragma unroll
-    for (int i = 0; i < 8; i++) U[i] = V[i] = 0;
-    if (c < nch) {
-        const int g = tile.chain0 + c;
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (i < nv) U[i] = cu[(size_t)g * nv + i];
-        pole = cpole[g];
-        int d0, k0;
-        choose_chunk_reg(fam, dirsL, U, pole - n, V, d0, k0);
-        if (d0 < 0 || k0 < 1) {
-            if (wave == 0 && half == 0) atomicOr(err, 1);
-            d0 = 0;
-            pole = n;
-        }
-        dir = d0;
-        kleft = k0;
-        if (wave == 0 && half == 0) {
-            const int col = colmapL[d0 * s + cg[g]];
-            if (col < 0) atomicOr(err, 2);
-            else Xbuf[c * XS + col] = (int8_t)1;  // balanced digits of 1
-        }
+    for (int idx = tid; idx < nch * F; idx += NT)
+        if (vx[tile.chain0 + idx / F].out < 0) hbuf[(size_t)tile.chain0 * F + idx] = 0;
+    for (int idx = tid; idx < nch * s; idx += NT) {
+        const int out = vx[tile.chain0 + idx / s].out;
+        if (out >= 0) store[(size_t)out * s + idx % s] = 0;
     }
     __syncthreads();
 
@@ -422,6 +434,59 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
     const double Bsplit = it.Bsplit, invBsplit = it.invBsplit, bias = it.bias;
     const int h = it.h, Bi = it.B, halfB = it.halfB, shift = it.shift;
     const uint32_t magic = it.magic;
+
+    // chain state (registers; identical in every lane of chain c)
+    int U[8], V[8], dir = 0, kleft = 0, pole = n, pend = n, vout = -1;
+#pragma unroll
+    for (int i = 0; i < 8; i++) U[i] = V[i] = 0;
+    if (c < nch) {
+        const int g = tile.chain0 + c;
+        const DevVec xv = vx[g];
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (i < nv) U[i] = cu[(size_t)g * nv + i];
+        pole = cpole[g];
+        pend = xv.pend;
+        vout = xv.out;
+        int d0, k0;
+        if (xv.dir >= 0) {  // one forced direction for the whole range
+            d0 = xv.dir;
+            k0 = pole - pend;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if (i < nv) V[i] = dirsL[d0 * nv + i];
+        } else {
+            choose_chunk_reg(fam, dirsL, U, pole - pend, V, d0, k0);
+        }
+        if (d0 < 0 || k0 < 1) {
+            if (wave == 0 && half == 0) atomicOr(err, 1);
+            d0 = 0;
+            pole = pend;
+        }
+        dir = d0;
+        kleft = k0;
+        if (xv.in < 0) {
+            if (wave == 0 && half == 0) {
+                const int col = colmapL[d0 * s + cg[g]];
+                if (col < 0) atomicOr(err, 2);
+                else Xbuf[c * XS + col] = (int8_t)1;  // balanced digits of 1
+            }
+        } else {
+            // start vector from the store: the lanes of chain c split its entries
+            for (int r = bin; r < s; r += 2 * NRT) {
+                const uint64_t x = store[(size_t)xv.in * s + r];
+                if (x == 0) continue;
+                const int col = colmapL[d0 * s + r];
+                if (col < 0) {
+                    atomicOr(err, 2);
+                    continue;
+                }
+                put_digits<D, XS>(Xbuf + c * XS + col, (double)x, Qd, bias, Bsplit, invBsplit, magic, shift, Bi,
+                                  halfB);
+            }
+        }
+    }
+    __syncthreads();
     int cur = 0;
 
     for (int step = 0; step < tile.steps; step++) {
@@ -443,17 +508,17 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
                     acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], acc[i + j], 0, 0, 0);
         }
         // bookkeeping of this lane's chain: exponent after the step, next direction
-        const bool act = pole > n;
+        const bool act = pole > pend;
         int up[8], Vn[8], dirn = dir, kleftn = kleft - 1;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
             up[i] = U[i] - (act ? V[i] : 0);
             Vn[i] = V[i];
         }
-        const bool more = act && pole - 1 > n;
+        const bool more = act && pole - 1 > pend;
         if (more && kleftn == 0) {
             int d0, k0;
-            choose_chunk_reg(fam, dirsL, up, pole - 1 - n, Vn, d0, k0);
+            choose_chunk_reg(fam, dirsL, up, pole - 1 - pend, Vn, d0, k0);
             if (d0 < 0 || k0 < 1) {
                 atomicOr(err, 1);
                 d0 = 0;
@@ -511,31 +576,9 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
                         atomicOr(err, 2);
                         continue;
                     }
-                    double xs = x + bias;
-                    if (xs >= Qd) xs -= Qd;
-                    double xh = floor(xs * invBsplit);
-                    double rl = fma(-xh, Bsplit, xs);
-                    if (rl < 0.0) {
-                        rl += Bsplit;
-                        xh -= 1.0;
-                    } else if (rl >= Bsplit) {
-                        rl -= Bsplit;
-                        xh += 1.0;
-                    }
-                    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
-                    int8_t *xp = Xn + c * XS + col;
-#pragma unroll
-                    for (int jd = 0; jd < DS; jd++) {
-                        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
-                        xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
-                        vl = qd;
-                    }
-#pragma unroll
-                    for (int jd = DS; jd < D; jd++) {
-                        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
-                        xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
-                        vh = qd;
-                    }
+                    put_digits<D, XS>(Xn + c * XS + col, x, Qd, bias, Bsplit, invBsplit, magic, shift, Bi, halfB);
+                } else if (vout >= 0) {
+                    store[(size_t)vout * s + r] = (uint64_t)x % it.q;  // combine point
                 } else {
                     int Ui = -1;
                     for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
@@ -576,10 +619,10 @@ bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
 
 template <int R, int KB, int DD, bool ZZ>
 static hipError_t launch_one4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
-                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
-                              const uint32_t *slots, int *err, hipStream_t stream) {
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, hipStream_t stream) {
     hipLaunchKernelGGL((k_reduce_mfma4<R, KB, DD, 3, ZZ>), dim3(ntiles), dim3(64 * R), 0, stream, fam, items, tiles, cu,
-                       cg, cpole, hbuf, slots, err);
+                       cg, cpole, vx, store, hbuf, slots, err);
     return hipGetLastError();
 }
 
@@ -590,16 +633,20 @@ bool mfma4_supports(const DevFamily &fam, int D) {
 }
 
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
-                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf,
-                               const uint32_t *slots, int *err, int D, bool z32, hipStream_t stream) {
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
+                               hipStream_t stream) {
     if (ntiles == 0) return hipSuccess;
     int nrt, nkb;
     if (!mfma4_supports(fam, D)) return hipErrorInvalidValue;
     mfma_shape(fam, nrt, nkb);
 #define CRF_LAUNCH4(R, KB, DD)                                                                                          \
     if (nrt == R && nkb == KB && D == DD) {                                                                             \
-        if (z32) return launch_one4<R, KB, DD, true>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream); \
-        return launch_one4<R, KB, DD, false>(fam, items, tiles, ntiles, cu, cg, cpole, hbuf, slots, err, stream);       \
+        if (z32)                                                                                                        \
+            return launch_one4<R, KB, DD, true>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,  \
+                                                stream);                                                                \
+        return launch_one4<R, KB, DD, false>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,     \
+                                             stream);                                                                   \
     }
     CRF_LAUNCH4(2, 2, 3)
     CRF_LAUNCH4(2, 2, 6)

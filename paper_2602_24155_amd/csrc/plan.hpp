@@ -1,0 +1,83 @@
+// Reduction plans: which start terms are reduced together, in which order,
+// and where like terms are combined (Section 3.4's reduction game, the
+// policies of Section 4).
+//
+// A plan is a list of phases.  In a phase every active term is reduced as one
+// vector from its pole to the phase's stop pole; between phases, terms whose
+// exponents u coincide (and hence whose poles coincide) may be combined.  The
+// value of a term is always  w (x) c : a vector w over Homog_{dn-n} times a row
+// c of coefficients over the basis columns.  Start terms are rank one (w a unit
+// vector e_gamma, c the Proposition 2.1 coefficients of their x^S-form
+// exponent); combining a group of terms with active columns A replaces them by
+// |A| vectors w_a = sum_j c_j[a] w_j with unit rows e_a.  A group is combined
+// only when it holds more vectors than active columns, so combining never
+// increases the number of vectors that are reduced.
+#pragma once
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+
+namespace crf {
+
+// One vector of a phase.  It starts at exponent u and pole `pole` from the
+// unit vector e_gamma (in < 0) or from store row `in`, is reduced to pole
+// `pend`, and ends in store row `out` (read by a later combine or phase) or,
+// when out < 0 (then pend = n), in the pole-n numerators of the final
+// Griffiths-Dwork step.  dir >= 0 forces one direction for the whole range
+// (pole - pend steps, valid by construction); dir < 0 reduces by Algorithm 3
+// chunks capped at pend.
+struct PlanVec {
+    int16_t u[kMaxVars];
+    int32_t pole, pend, gamma, in, out, dir;
+    int32_t crow;  // coefficient row used by the final assembly (see ItemPlan)
+};
+
+// A store row built between two phases: row = sum_{j in [m0, m1)} alpha_j src_j,
+// src_j >= 0 a store row, src_j < 0 the unit vector e_{-src_j - 1}.
+struct PlanComb {
+    int32_t row, m0, m1;
+};
+
+struct ItemPlan {
+    int policy = 0;
+    std::vector<std::vector<PlanVec>> phase;  // phase t, each sorted by steps (pole - pend) descending
+    std::vector<std::vector<PlanComb>> comb;  // comb[t]: rows built before phase t (comb[0] empty)
+    std::vector<int32_t> msrc;                // members of every PlanComb
+    std::vector<u64> malpha;
+    int32_t nrows = 0;                        // store rows (s residues each)
+    // coefficient rows: crow < nchain is start row crow of ItemSetup::coef,
+    // crow >= nchain the unit row of basis column crow - nchain
+    int64_t column_steps = 0, chunks = 0, vectors = 0, merged_terms = 0, combined_groups = 0;
+};
+
+// A term of the reduction game as the planner sees it.
+struct PlanTerm {
+    int16_t u[kMaxVars];
+    int32_t pole;
+    int32_t src;   // store row, or -(gamma + 1) for a unit start vector
+    int32_t crow;
+    uint64_t cols; // active basis columns
+};
+
+// Direction chooser of the learned policy: for the terms of one phase (all
+// reduced to stop pole `pend`), dir_out[t] = a direction index valid for the
+// whole range pole - pend, or -1 for Algorithm 3 chunks.
+using DirChooser = std::function<bool(const std::vector<PlanTerm> &terms, int pend, std::vector<int32_t> &dir_out)>;
+
+// Algorithm 3 for exponent U (greedy v); false if no direction exists.
+bool greedy_direction(const Family &fam, const int *U, int *v);
+// Index of direction v among fam.dirs, or -1.
+int direction_index(const Family &fam, const int *v);
+// Whether direction v can be used for k consecutive steps from exponent U:
+// U - k v >= 0, and i in S with v_i = 0 implies U_i = 0.
+bool direction_valid(const Family &fam, const int *U, const int *v, int k);
+
+// Builds the plan of one item for `policy` (cr_policy).  Requires b <= 64 for
+// the combining policies.  chooser is used by CR_POLICY_LEARNED only.
+bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err,
+               const DirChooser *chooser = nullptr);
+
+}  // namespace crf
