@@ -78,6 +78,11 @@ typedef enum {
  * |A| vectors sum_j c_j[a] w_j (one per column a in A) when it holds more
  * than |A| terms; smaller groups are left as they are. */
 
+/* Learned policy model (opaque): a fully connected fp32 network 16 -> 128 ->
+ * 128 -> 1 (ReLU) that scores (term, candidate direction) pairs of a p-chunk
+ * phase; see cr_mlp_create. */
+typedef struct cr_mlp cr_mlp;
+
 /* A family of hypersurfaces that share nvars, degree and S; p may vary per item. */
 typedef struct {
     int32_t nvars;    /* n + 1 */
@@ -90,6 +95,9 @@ typedef struct {
                          the accumulators when the family's tables fit it, else the 64-bit VALU
                          kernel), 1 = 64-bit VALU kernel, 2 = int8-digit MFMA kernel with the
                          gather through LDS */
+    int32_t pad_;     /* set to 0 */
+    cr_mlp *mlp;      /* model of CR_POLICY_LEARNED (required then, ignored otherwise); the
+                         library uses its device scratch, so one model serves one call at a time */
 } cr_family;
 
 /* Per-call statistics (all counts are summed over the batch). */
@@ -109,7 +117,8 @@ typedef struct {
     int32_t engine;          /* kernel that ran: 0 / 2 = int8-digit MFMA (register / LDS gather), 1 = 64-bit VALU */
     int32_t policy;          /* policy whose plan ran */
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
-    int32_t pad_;
+    int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a
+                                plain policy's and were reduced with the cheaper plain plan */
 } cr_stats;
 
 /* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},
@@ -167,6 +176,61 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
  * is M column_steps + S chunks + D merged_terms).  Not available for
  * CR_POLICY_LEARNED (whose plan needs the model): CR_EINVAL. */
 cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs, cr_stats *stats);
+
+/*
+ * Learned policy (the benchmark spec's extension; the paper's Section 4.4 asks
+ * for better policies).  The network's inputs for a term at exponent u of a
+ * p-chunk phase that ends at pole `stop`, and a direction v valid for all
+ * k = pole - stop steps (u' = u - k v):
+ *   x[0..5]  u_i/|u| (zero padded)     x[6..11] v_i/d (zero padded)
+ *   x[12]    log(1 + |A|)/4            x[13]    (stop - n)/(p (n + 1))
+ *   x[14]    log(1 + g)/4, g = other terms that land on u' in the plain p-chunk
+ *            plan or already wait there; A = their active basis columns
+ *   x[15]    1 if v is Algorithm 3's direction for u, else 0
+ * Training label: the vectors the choice adds at u' (min(g + 1, |A u A_t|) -
+ * min(g, |A|), A the active basis columns there, A_t the term's) times
+ * (stop - n)/(p (n + 1)).  The policy takes, for every term, the candidate of
+ * lowest score (ties: lowest direction index; no candidate: Algorithm 3
+ * chunks), then judges the plan by the game cost of Section 3.4 with M = 1,
+ * S = 0, D = 1/8 against the depth-first and p-chunk plans and reduces with
+ * the cheapest.  The policy changes which vectors are reduced, never the bits.
+ *
+ * Parameters (CR_MLP_PARAMS floats, row-major, W[k][j] takes input k to unit j):
+ *   W1[16][128], b1[128], W2[128][128], b2[128], w3[128], b3.
+ */
+#define CR_MLP_INPUTS 16
+#define CR_MLP_HIDDEN 128
+#define CR_MLP_PARAMS 18817
+
+typedef struct {
+    int32_t epochs;    /* passes over the rows */
+    int32_t batch;     /* rows per Adam step (>= 1) */
+    float lr, beta1, beta2, eps;  /* Adam; zeros select 1e-3, 0.9, 0.999, 1e-8 */
+    uint64_t seed;     /* row shuffling */
+} cr_train_opts;
+
+/* New model on the current HIP device.  weights: CR_MLP_PARAMS floats, or NULL
+ * for a seeded initialisation (weights uniform in +-1/sqrt(fan_in), biases 0). */
+cr_status cr_mlp_create(const float *weights, uint64_t seed, cr_mlp **out);
+cr_status cr_mlp_destroy(cr_mlp *m);
+/* Copies the CR_MLP_PARAMS parameters to host memory. */
+cr_status cr_mlp_weights(const cr_mlp *m, float *out);
+/* Scores of `rows` input rows (host x[rows * 16] -> host y[rows]), on the GPU. */
+cr_status cr_mlp_forward(cr_mlp *m, int32_t rows, const float *x, float *y, void *hip_stream);
+/* Gradient of the loss (1/rows) sum (y - t)^2 with respect to the parameters
+ * (host grad[CR_MLP_PARAMS]) and the loss, on the GPU. */
+cr_status cr_mlp_grad(cr_mlp *m, int32_t rows, const float *x, const float *t, float *grad, float *loss,
+                      void *hip_stream);
+/* Adam on the GPU over host rows (x[rows * 16], labels t[rows]); loss[epochs]
+ * (may be NULL) receives the mean minibatch loss of each epoch. */
+cr_status cr_mlp_train(cr_mlp *m, int32_t rows, const float *x, const float *t, const cr_train_opts *opts,
+                       float *loss, void *hip_stream);
+/* Training rows of one hypersurface: the inputs and labels of every (term,
+ * candidate) pair of its plain p-chunk plan.  With x == NULL only *rows is
+ * set (the count); otherwise at most cap rows are written (CR_EINVAL if the
+ * count exceeds cap). Host only. */
+cr_status cr_trace_policy(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t cap, float *x, float *t,
+                          int32_t *rows);
 
 /* Frees the library's cached device and host workspaces. */
 cr_status cr_release(void);

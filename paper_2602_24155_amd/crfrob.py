@@ -17,13 +17,23 @@ CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
 CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_policy_cost", "cr_release", "cr_last_error"]
+           "cr_frobenius_batch", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
+           "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_release", "cr_last_error"]
 
 
 class cr_family(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
                 ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32),
-                ("engine", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("pad_", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+
+
+class cr_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+CR_MLP_INPUTS, CR_MLP_HIDDEN, CR_MLP_PARAMS = 16, 128, 18817
 
 
 class cr_stats(ctypes.Structure):
@@ -34,7 +44,7 @@ class cr_stats(ctypes.Structure):
                 ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double),
                 ("assemble_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("engine", ctypes.c_int32), ("policy", ctypes.c_int32),
-                ("phases", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("phases", ctypes.c_int32), ("fallbacks", ctypes.c_int32)]
 
 
 class CrError(RuntimeError):
@@ -61,6 +71,14 @@ def lib():
         L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
                                          P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
         L.cr_policy_cost.argtypes = [P(cr_family), i32, P(u32), P(cr_stats)]
+        f32, vp = ctypes.c_float, ctypes.c_void_p
+        L.cr_mlp_create.argtypes = [P(f32), u64, P(vp)]
+        L.cr_mlp_destroy.argtypes = [vp]
+        L.cr_mlp_weights.argtypes = [vp, P(f32)]
+        L.cr_mlp_forward.argtypes = [vp, i32, P(f32), P(f32), vp]
+        L.cr_mlp_grad.argtypes = [vp, i32, P(f32), P(f32), P(f32), P(f32), vp]
+        L.cr_mlp_train.argtypes = [vp, i32, P(f32), P(f32), P(cr_train_opts), P(f32), vp]
+        L.cr_trace_policy.argtypes = [P(cr_family), i32, P(u32), i32, P(f32), P(f32), P(i32)]
         L.cr_release.argtypes = []
         L.cr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -82,8 +100,8 @@ def _ptr(a, ctype):
 ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS = 0, 1, 2
 
 
-def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO):
-    return cr_family(nvars, degree, s_mask, policy, r, n_series, engine)
+def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO, mlp=None):
+    return cr_family(nvars, degree, s_mask, policy, r, n_series, engine, 0, mlp.handle if mlp is not None else None)
 
 
 def cr_query_dims(nvars, degree):
@@ -157,6 +175,72 @@ def cr_policy_cost(fam, p, coeffs):
     stats = cr_stats()
     _check(lib().cr_policy_cost(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), ctypes.byref(stats)))
     return stats
+
+
+class Mlp:
+    """Owner of a cr_mlp handle (the learned policy's network on the GPU)."""
+
+    def __init__(self, weights=None, seed=0):
+        h = ctypes.c_void_p()
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+            assert w.shape == (CR_MLP_PARAMS,)
+        _check(lib().cr_mlp_create(_ptr(w, ctypes.c_float) if w is not None else None, seed, ctypes.byref(h)))
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            lib().cr_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        out = np.zeros(CR_MLP_PARAMS, dtype=np.float32)
+        _check(lib().cr_mlp_weights(self.handle, _ptr(out, ctypes.c_float)))
+        return out
+
+    def forward(self, x, stream=None):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1, CR_MLP_INPUTS))
+        y = np.zeros(x.shape[0], dtype=np.float32)
+        _check(lib().cr_mlp_forward(self.handle, x.shape[0], _ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float),
+                                    ctypes.c_void_p(stream or 0)))
+        return y
+
+    def grad(self, x, t, stream=None):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1, CR_MLP_INPUTS))
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float32))
+        g = np.zeros(CR_MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().cr_mlp_grad(self.handle, x.shape[0], _ptr(x, ctypes.c_float), _ptr(t, ctypes.c_float),
+                                 _ptr(g, ctypes.c_float), ctypes.byref(loss), ctypes.c_void_p(stream or 0)))
+        return g, loss.value
+
+    def train(self, x, t, epochs=10, batch=256, lr=0.0, seed=0, stream=None):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1, CR_MLP_INPUTS))
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float32))
+        opts = cr_train_opts(epochs, batch, lr, 0.0, 0.0, 0.0, seed)
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        _check(lib().cr_mlp_train(self.handle, x.shape[0], _ptr(x, ctypes.c_float), _ptr(t, ctypes.c_float),
+                                  ctypes.byref(opts), _ptr(losses, ctypes.c_float), ctypes.c_void_p(stream or 0)))
+        return losses[:epochs]
+
+
+def cr_trace_policy(fam, p, coeffs):
+    """Training rows (inputs, labels) of one hypersurface's plain p-chunk plan."""
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32))
+    n = ctypes.c_int32()
+    _check(lib().cr_trace_policy(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), 0, None, None, ctypes.byref(n)))
+    x = np.zeros((n.value, CR_MLP_INPUTS), dtype=np.float32)
+    t = np.zeros(n.value, dtype=np.float32)
+    _check(lib().cr_trace_policy(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), n.value, _ptr(x, ctypes.c_float),
+                                 _ptr(t, ctypes.c_float), ctypes.byref(n)))
+    return x, t
 
 
 def cr_release():

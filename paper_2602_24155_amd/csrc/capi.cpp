@@ -15,6 +15,7 @@
 
 #include "device_layout.hpp"
 #include "host.hpp"
+#include "mlp.hpp"
 #include "plan.hpp"
 
 namespace crf {
@@ -43,6 +44,14 @@ using namespace crf;
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace crf {
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace crf
+
+namespace {
 
 cr_status fail(cr_status st, const std::string &msg) {
     g_err = msg;
@@ -186,7 +195,125 @@ bool check_family(const cr_family *fam, std::string &err) {
     return true;
 }
 
+// CR_POLICY_LEARNED: the p-chunk phases of every item advance together; per
+// phase the candidates of all items are scored in one network evaluation on
+// the GPU and every term takes its lowest-scoring candidate.  Each finished
+// plan is judged against the depth-first and p-chunk plans (plan_cost) and
+// the cheapest is kept.
+bool plan_learned(const Family &F, std::vector<ItemSetup> &items, std::vector<cr_status> &st,
+                  std::vector<std::string> &errs, std::vector<ItemPlan> &plans, cr_mlp *mlp, hipStream_t stream,
+                  int &fallbacks, std::string &err) {
+    const int count = (int)items.size();
+    std::vector<PChunkPlanner> pl(count);
+    std::vector<char> on(count, 0);
+    for (int i = 0; i < count; i++) {
+        if (st[i] != CR_OK) continue;
+        if (!pl[i].init(F, items[i], CR_POLICY_LEARNED, errs[i])) {
+            st[i] = CR_EINVAL;
+            continue;
+        }
+        on[i] = 1;
+    }
+    std::vector<std::vector<CandRow>> rows(count);
+    std::vector<char> active(count, 0);
+    for (;;) {
+        parallel_for(count, [&](int i) {
+            active[i] = 0;
+            rows[i].clear();
+            if (!on[i] || st[i] != CR_OK) return;
+            if (!pl[i].begin_phase()) return;
+            active[i] = 1;
+            pl[i].candidates(rows[i]);
+        });
+        std::vector<size_t> r0(count + 1, 0);
+        bool any = false;
+        for (int i = 0; i < count; i++) {
+            r0[i + 1] = r0[i] + rows[i].size();
+            any = any || active[i];
+        }
+        if (!any) break;
+        const size_t R = r0[count];
+        if (R >= (size_t)INT32_MAX) {
+            err = "too many candidate rows";
+            return false;
+        }
+        std::vector<float> X(R * kMlpIn), Y(R);
+        for (int i = 0; i < count; i++)
+            for (size_t k = 0; k < rows[i].size(); k++)
+                std::memcpy(&X[(r0[i] + k) * kMlpIn], rows[i][k].x, sizeof(float) * kMlpIn);
+        if (!mlp_score(mlp, X.data(), (int)R, Y.data(), stream, err)) return false;
+        parallel_for(count, [&](int i) {
+            if (!active[i]) return;
+            std::vector<int32_t> dir(pl[i].act.size(), -1);
+            std::vector<float> best(pl[i].act.size(), 0.f);
+            for (size_t k = 0; k < rows[i].size(); k++) {
+                const CandRow &r = rows[i][k];
+                const float y = Y[r0[i] + k];
+                if (dir[r.term] < 0 || y < best[r.term]) {  // rows come in increasing direction order
+                    dir[r.term] = r.dir;
+                    best[r.term] = y;
+                }
+            }
+            if (!pl[i].end_phase(dir, errs[i])) {
+                st[i] = CR_ESELFCHECK;
+                on[i] = 0;
+            }
+        });
+    }
+    std::atomic<int> fb{0};
+    parallel_for(count, [&](int i) {
+        if (!on[i] || st[i] != CR_OK) return;
+        plans[i] = std::move(pl[i].plan);
+        for (int alt : {CR_POLICY_P_CHUNK, CR_POLICY_DEPTH_FIRST}) {
+            ItemPlan other;
+            std::string e2;
+            if (plan_item(F, items[i], alt, other, e2) && plan_cost(other) < plan_cost(plans[i])) {
+                if (plans[i].policy == CR_POLICY_LEARNED) fb++;
+                plans[i] = std::move(other);
+            }
+        }
+    });
+    fallbacks = fb.load();
+    return true;
+}
+
 }  // namespace
+
+namespace crf {
+bool trace_item(const cr_family *fam, int p, const uint32_t *coeffs, std::vector<CandRow> &rows, std::string &err,
+                cr_status &st) {
+    if (!check_family(fam, err)) {
+        st = CR_EINVAL;
+        return false;
+    }
+    FamilyEntry *fe;
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        fe = get_family(fam, err);
+    }
+    if (!fe) {
+        st = CR_EINVAL;
+        return false;
+    }
+    ItemSetup it;
+    st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err);
+    if (st != CR_OK) return false;
+    PChunkPlanner pc;
+    if (!pc.init(fe->fam, it, CR_POLICY_P_CHUNK, err)) {
+        st = CR_EINVAL;
+        return false;
+    }
+    while (pc.begin_phase()) {
+        pc.candidates(rows);
+        std::vector<int32_t> none(pc.act.size(), -1);
+        if (!pc.end_phase(none, err)) {
+            st = CR_ESELFCHECK;
+            return false;
+        }
+    }
+    return true;
+}
+}  // namespace crf
 
 extern "C" {
 
@@ -261,7 +388,7 @@ cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs
     cr_status st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err);
     if (st != CR_OK) return fail(st, err);
     ItemPlan plan;
-    if (!plan_item(fe->fam, it, fam->policy, plan, err, nullptr)) return fail(CR_EINVAL, err);
+    if (!plan_item(fe->fam, it, fam->policy, plan, err)) return fail(CR_EINVAL, err);
     std::memset(stats, 0, sizeof(*stats));
     stats->start_blocks = it.nchain();
     stats->column_steps = plan.column_steps;
@@ -322,14 +449,14 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     std::vector<std::string> errs(count);
     std::vector<DigitParams> dps(count);
     std::vector<char> digit_ok(count, 0);
-    const DirChooser *chooser = nullptr;
     parallel_for(count, [&](int i) {
         st[i] = setup_item(F, primes[i], coeffs + (size_t)i * nco, fam->r, fam->n_series, items[i], errs[i]);
         if (st[i] == CR_OK && items[i].b != b) {
             st[i] = CR_ESELFCHECK;
             errs[i] = "basis size differs from the Hodge numbers";
         }
-        if (st[i] == CR_OK && !plan_item(F, items[i], policy, plans[i], errs[i], chooser)) st[i] = CR_EINVAL;
+        if (st[i] == CR_OK && policy != CR_POLICY_LEARNED && !plan_item(F, items[i], policy, plans[i], errs[i]))
+            st[i] = CR_EINVAL;
         if (st[i] == CR_OK && want_mfma) {
             ItemSetup &it = items[i];
             int umax = 0;
@@ -342,6 +469,12 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             }
         }
     });
+    int fallbacks = 0;
+    if (policy == CR_POLICY_LEARNED) {
+        if (!fam->mlp) return fail(CR_EINVAL, "CR_POLICY_LEARNED needs a model (cr_family.mlp)");
+        std::string lerr;
+        if (!plan_learned(F, items, st, errs, plans, fam->mlp, stream, fallbacks, lerr)) return fail(CR_EDEVICE, lerr);
+    }
     const double setup_ms = ms_since(t0);
 
     std::vector<int> live;
@@ -701,6 +834,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         stats->engine = use_mfma ? (use_bins ? 0 : 2) : 1;
         stats->policy = policy;
         stats->phases = nphase;
+        stats->fallbacks = fallbacks;
         stats->assemble_ms = asm_ms;
         stats->finish_ms = finish_ms;
     }

@@ -14,7 +14,6 @@
 // increases the number of vectors that are reduced.
 #pragma once
 #include <cstdint>
-#include <functional>
 #include <string>
 #include <vector>
 
@@ -62,10 +61,49 @@ struct PlanTerm {
     uint64_t cols; // active basis columns
 };
 
-// Direction chooser of the learned policy: for the terms of one phase (all
-// reduced to stop pole `pend`), dir_out[t] = a direction index valid for the
-// whole range pole - pend, or -1 for Algorithm 3 chunks.
-using DirChooser = std::function<bool(const std::vector<PlanTerm> &terms, int pend, std::vector<int32_t> &dir_out)>;
+// Inputs of the learned policy's scoring network, one row per (term,
+// candidate direction) of a p-chunk phase.  For a term at exponent u reduced
+// by k = pole - stop steps with direction v to u' = u - k v:
+//   x[0..5]  u_i / |u|            x[6..11] v_i / d
+//   x[12]    log(1 + |A|) / 4     x[13]    (stop - n) / (p (n + 1))
+//   x[14]    log(1 + g) / 4, g = terms landing at u' in the plain p-chunk plan
+//            (other than this term) plus terms already waiting at u'; A = the
+//            active basis columns of those terms
+//   x[15]    1 if v is Algorithm 3's direction for u
+// label = the vectors this choice adds at u' (min(g + 1, |A + A_t|) -
+// min(g, |A|), A the active columns there, A_t the term's) times
+// (stop - n) / (p (n + 1)): the remaining work it causes.
+constexpr int kMlpIn = 16;
+struct CandRow {
+    int32_t term, dir;
+    float x[kMlpIn];
+    float label;
+};
+
+// The p-chunk phases of one item as a state machine, so that the directions
+// of a whole batch can be chosen phase by phase (one network evaluation per
+// phase for every item).
+struct PChunkPlanner {
+    const Family *fam = nullptr;
+    const ItemSetup *it = nullptr;
+    ItemPlan plan;
+    std::vector<PlanTerm> terms;
+    std::vector<int> act;  // terms of the current phase
+    int stop = 0;
+    bool started = false, finished = false;
+    bool init(const Family &f, const ItemSetup &s, int policy, std::string &err);
+    // Selects the next phase; false when every term has reached pole n.
+    bool begin_phase();
+    // Candidate rows of the current phase (features and labels).
+    void candidates(std::vector<CandRow> &rows) const;
+    // Reduces the phase with dir[a] for act[a] (-1: Algorithm 3 chunks), then combines.
+    bool end_phase(const std::vector<int32_t> &dir, std::string &err);
+};
+
+// Game cost used to judge a plan (Section 3.4 with M = 1 per column step,
+// S = 0 per chunk: no matrix is materialised per chunk here, and D = 1/8 per
+// merged term: a combine reads one vector instead of an s x s product).
+inline double plan_cost(const ItemPlan &p) { return (double)p.column_steps + 0.125 * (double)p.merged_terms; }
 
 // Algorithm 3 for exponent U (greedy v); false if no direction exists.
 bool greedy_direction(const Family &fam, const int *U, int *v);
@@ -75,9 +113,8 @@ int direction_index(const Family &fam, const int *v);
 // U - k v >= 0, and i in S with v_i = 0 implies U_i = 0.
 bool direction_valid(const Family &fam, const int *U, const int *v, int k);
 
-// Builds the plan of one item for `policy` (cr_policy).  Requires b <= 64 for
-// the combining policies.  chooser is used by CR_POLICY_LEARNED only.
-bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err,
-               const DirChooser *chooser = nullptr);
+// Builds the plan of one item for a plain policy (depth-first, p-chunk,
+// var-by-var).  Requires b <= 64 for the combining policies.
+bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err);
 
 }  // namespace crf

@@ -1,0 +1,108 @@
+"""GPU kernels of the learned policy's network against the fp64 oracle, and
+the learned policy end to end (its plans change the work, never the bits).
+
+Tolerances (fp32 kernels vs fp64 oracle): the forward pass sums at most 128
+products of magnitude <= ~10 per unit, so |y_gpu - y| <= 1e-4 (1 + |y|); the
+gradient sums over rows in a different order, so it is compared in norm
+(relative 1e-5) and entrywise against 1e-4 of its largest entry."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_2602_24155_amd import crfrob as C
+from tests.gpu_common import assert_item_matches_oracle, workload_items
+
+pytestmark = pytest.mark.gpu
+
+
+def rows(R, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-0.5, 2.0, (R, OM.IN)).astype(np.float32)
+    t = rng.uniform(0.0, 1.5, R).astype(np.float32)
+    return x, t
+
+
+@pytest.mark.parametrize("R", [1, 63, 64, 65, 200])
+def test_forward_matches_oracle(R):
+    w = OM.init(3).astype(np.float32)
+    m = C.Mlp(weights=w)
+    x, _t = rows(R, R)
+    y = m.forward(x)
+    want = OM.forward(w.astype(np.float64), x.astype(np.float64))
+    assert np.all(np.abs(y - want) <= 1e-4 * (1 + np.abs(want)))
+    assert np.array_equal(m.weights(), w)
+
+
+@pytest.mark.parametrize("R", [1, 65, 200, 1000])
+def test_gradient_matches_oracle(R):
+    w = OM.init(5).astype(np.float32)
+    m = C.Mlp(weights=w)
+    x, t = rows(R, 100 + R)
+    g, L = m.grad(x, t)
+    g64, L64 = OM.grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(L - L64) <= 1e-5 * (1 + L64)
+    assert np.linalg.norm(g - g64) <= 1e-5 * np.linalg.norm(g64) + 1e-7
+    assert np.all(np.abs(g - g64) <= 1e-4 * np.abs(g64).max())
+    g2, _ = m.grad(x, t)
+    assert np.array_equal(g, g2), "the gradient is not reproducible"
+
+
+def test_first_adam_step():
+    """One Adam step over all rows from zero moments moves every weight by
+    -lr g / (|g| + eps) (bias-corrected moments of a single step)."""
+    w = OM.init(9).astype(np.float32)
+    m = C.Mlp(weights=w)
+    x, t = rows(300, 9)
+    g64, _ = OM.grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    m.train(x, t, epochs=1, batch=300, lr=1e-3, seed=1)
+    dw = m.weights().astype(np.float64) - w.astype(np.float64)
+    big = np.abs(g64) > 1e-3 * np.abs(g64).max()
+    want = -1e-3 * g64 / (np.abs(g64) + 1e-8)
+    assert np.all(np.abs(dw[big] - want[big]) <= 2e-5)
+
+
+def test_seeded_initialisation_is_reproducible():
+    a, b = C.Mlp(seed=11), C.Mlp(seed=11)
+    wa = a.weights()
+    assert np.array_equal(wa, b.weights()) and np.abs(wa).max() <= 1 / np.sqrt(16)
+    assert not np.array_equal(wa, C.Mlp(seed=12).weights())
+
+
+def training_rows():
+    xs, ts = [], []
+    for nv, d, name, js in [(3, 4, "quartic_curve_f7", [0]), (3, 5, "quintic_curves_mixed", range(12, 16)),
+                            (3, 5, "quintic_curves_p31", [0, 3])]:
+        fam = C.family(nv, d)
+        for p, c in workload_items(name, js):
+            x, t = C.cr_trace_policy(fam, p, c)
+            xs.append(x)
+            ts.append(t)
+    return np.concatenate(xs), np.concatenate(ts)
+
+
+def test_train_and_reduce_with_learned_policy():
+    x, t = training_rows()
+    assert x.shape[0] > 10000
+    m = C.Mlp(seed=2)
+    losses = m.train(x, t, epochs=8, batch=512, lr=2e-3, seed=4)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
+    items = workload_items("quintic_curves_mixed", range(6))
+    fam = C.family(3, 5, policy=C.CR_POLICY_LEARNED, mlp=m)
+    res = C.cr_frobenius_batch(fam, [p for p, _ in items], [c for _, c in items])
+    st = res["stats"]
+    assert st.policy == C.CR_POLICY_LEARNED and 0 <= st.fallbacks <= len(items)
+    for i, (p, c) in enumerate(items):
+        assert_item_matches_oracle(res, i, 3, 5, p, c)
+    # judged plans never cost more column steps than the plain p-chunk plans
+    plain = sum(C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_P_CHUNK), p, c).column_steps
+                + C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_P_CHUNK), p, c).merged_terms / 8.0
+                for p, c in items)
+    assert st.column_steps + st.merged_terms / 8.0 <= plain + 1e-9
+    m.close()
+
+
+def test_learned_policy_without_model_is_an_error():
+    items = workload_items("quartic_curve_f7", [0])
+    res = C.cr_frobenius_batch(C.family(3, 4, policy=C.CR_POLICY_LEARNED), [items[0][0]], [items[0][1]],
+                               raise_on_error=False)
+    assert res["status"] == C.CR_EINVAL
