@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="quintic_curves_p31")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--policy", default="auto", choices=["auto", "depth-first", "p-chunk", "var-by-var"],
+                    help="reduction policy; auto = the autotuner's choice (measured before the warmup)")
+    ap.add_argument("--launch", default="auto", choices=["auto", "grid", "persistent", "graph"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (profiler calibration "
                          "of the FETCH_SIZE / WRITE_SIZE counters)")
@@ -114,11 +117,26 @@ def main():
     items = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(fam, p, c)) for j in range(w.count)]
     primes = [p for p, _ in items]
     coeffs = [c for _, c in items]
+    pol_names = ["depth-first", "p-chunk", "var-by-var", "learned"]
+    launch_names = ["grid", "persistent", "graph"]
+    tuning = None
+    if args.policy == "auto" or args.launch == "auto":
+        tu = C.cr_autotune(fam, primes, coeffs, trials=2, stream=stream)
+        tuning = {"%s/%s" % (pol_names[k // 3], launch_names[k % 3]): round(tu.ms[k], 2)
+                  for k in range(12) if tu.ms[k] > 0}
+        if args.policy == "auto":
+            fam.policy = tu.best_policy
+        if args.launch == "auto":
+            fam.launch = tu.best_launch
+    if args.policy != "auto":
+        fam.policy = pol_names.index(args.policy)
+    if args.launch != "auto":
+        fam.launch = launch_names.index(args.launch)
 
     for _ in range(args.warmup):
         C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
     torch.cuda.synchronize()
-    tot = {"reduce_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
+    tot = {"reduce_ms": 0.0, "combine_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
@@ -155,8 +173,10 @@ def main():
         "dtype": "u64 residues mod p^M (int8-limb / int32 exact products)",
         "data": "synthetic: seeded random dense smooth curves, coefficients uniform in F_p",
         "config": {"workload": args.workload, "count": len(items), "nvars": w.nvars, "degree": w.degree,
-                   "primes": sorted(set(primes)), "policy": "depth-first",
-                   "start_blocks": st.start_blocks, "column_steps_per_step": st.column_steps},
+                   "primes": sorted(set(primes)), "policy": pol_names[fam.policy],
+                   "launch": launch_names[fam.launch], "autotune_ms_per_call": tuning,
+                   "start_blocks": st.start_blocks, "column_steps_per_step": st.column_steps,
+                   "vectors_per_step": st.vectors, "merged_terms_per_step": st.merged_terms},
         "matvecs_per_s": st.column_steps / red_s,
         "breakdown_ms": {k: v / args.steps for k, v in tot.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",

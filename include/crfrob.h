@@ -95,7 +95,12 @@ typedef struct {
                          the accumulators when the family's tables fit it, else the 64-bit VALU
                          kernel), 1 = 64-bit VALU kernel, 2 = int8-digit MFMA kernel with the
                          gather through LDS */
-    int32_t pad_;     /* set to 0 */
+    int32_t launch;   /* reduction launches (int8-digit register-gather kernel; the others always
+                         use mode 0): 0 = one workgroup per tile of 32 vectors; 1 = persistent:
+                         one grid sized to the device's resident capacity drains the tiles
+                         (longest first) through an atomic counter; 2 = as 1, with the launches
+                         of a sub-batch captured once into a hipGraph and replayed while the
+                         launch parameters repeat */
     cr_mlp *mlp;      /* model of CR_POLICY_LEARNED (required then, ignored otherwise); the
                          library uses its device scratch, so one model serves one call at a time */
 } cr_family;
@@ -231,6 +236,20 @@ cr_status cr_mlp_train(cr_mlp *m, int32_t rows, const float *x, const float *t, 
  * count exceeds cap). Host only. */
 cr_status cr_trace_policy(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t cap, float *x, float *t,
                           int32_t *rows);
+
+/* Autotuner: runs the batch under every (policy, launch) pair -- policies
+ * depth-first, p-chunk, var-by-var (and learned when fam->mlp is set), launch
+ * modes 0, 1, 2 -- once to warm up and `trials` times timed (wall clock of
+ * whole cr_frobenius_batch calls), and returns the fastest in best_policy /
+ * best_launch.  ms[policy * 3 + launch] receives the mean time of each pair
+ * (-1 when not run; room for 12 entries).  Every pair gives the same bits. */
+typedef struct {
+    int32_t best_policy, best_launch;
+    double best_ms;
+    double ms[12];
+} cr_tuning;
+cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
+                      int32_t trials, cr_tuning *out, void *hip_stream);
 
 /* Frees the library's cached device and host workspaces. */
 cr_status cr_release(void);

@@ -18,13 +18,19 @@ CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNE
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
            "cr_frobenius_batch", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
-           "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_release", "cr_last_error"]
+           "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_autotune", "cr_release",
+           "cr_last_error"]
 
 
 class cr_family(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
                 ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32),
-                ("engine", ctypes.c_int32), ("pad_", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("engine", ctypes.c_int32), ("launch", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+
+
+class cr_tuning(ctypes.Structure):
+    _fields_ = [("best_policy", ctypes.c_int32), ("best_launch", ctypes.c_int32), ("best_ms", ctypes.c_double),
+                ("ms", ctypes.c_double * 12)]
 
 
 class cr_train_opts(ctypes.Structure):
@@ -79,6 +85,7 @@ def lib():
         L.cr_mlp_grad.argtypes = [vp, i32, P(f32), P(f32), P(f32), P(f32), vp]
         L.cr_mlp_train.argtypes = [vp, i32, P(f32), P(f32), P(cr_train_opts), P(f32), vp]
         L.cr_trace_policy.argtypes = [P(cr_family), i32, P(u32), i32, P(f32), P(f32), P(i32)]
+        L.cr_autotune.argtypes = [P(cr_family), i32, P(i32), P(u32), i32, P(cr_tuning), vp]
         L.cr_release.argtypes = []
         L.cr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -100,8 +107,13 @@ def _ptr(a, ctype):
 ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS = 0, 1, 2
 
 
-def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO, mlp=None):
-    return cr_family(nvars, degree, s_mask, policy, r, n_series, engine, 0, mlp.handle if mlp is not None else None)
+LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
+
+
+def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO, mlp=None,
+           launch=LAUNCH_GRID):
+    return cr_family(nvars, degree, s_mask, policy, r, n_series, engine, launch,
+                     mlp.handle if mlp is not None else None)
 
 
 def cr_query_dims(nvars, degree):
@@ -241,6 +253,17 @@ def cr_trace_policy(fam, p, coeffs):
     _check(lib().cr_trace_policy(ctypes.byref(fam), p, _ptr(c, ctypes.c_uint32), n.value, _ptr(x, ctypes.c_float),
                                  _ptr(t, ctypes.c_float), ctypes.byref(n)))
     return x, t
+
+
+def cr_autotune(fam, primes, coeffs, trials=2, stream=None):
+    """Fastest (policy, launch) for this batch; returns the cr_tuning record."""
+    primes = np.ascontiguousarray(np.asarray(primes, dtype=np.int32))
+    nco = cr_query_dims(fam.nvars, fam.degree)[0]
+    co = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32).reshape(primes.shape[0], nco))
+    out = cr_tuning()
+    _check(lib().cr_autotune(ctypes.byref(fam), primes.shape[0], _ptr(primes, ctypes.c_int32),
+                             _ptr(co, ctypes.c_uint32), trials, ctypes.byref(out), ctypes.c_void_p(stream or 0)))
+    return out
 
 
 def cr_release():

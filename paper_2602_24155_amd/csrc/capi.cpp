@@ -35,7 +35,8 @@ bool mfma_supports_digits(int D);
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                                const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
                                uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
-                               hipStream_t stream);
+                               int pgrid, int *queue, hipStream_t stream);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
 }  // namespace crf
 
@@ -102,7 +103,14 @@ struct FamilyEntry {
 };
 
 std::mutex g_mutex;
-Arena g_arena;
+Arena g_arenas[2];  // alternate between consecutive sub-batches of a call
+std::map<std::string, hipGraphExec_t> g_graphs;  // captured reduction launches by launch signature
+hipStream_t g_capture = nullptr;                 // private stream used for graph capture
+
+void clear_graphs() {
+    for (auto &g : g_graphs) (void)hipGraphExecDestroy(g.second);
+    g_graphs.clear();
+}
 std::map<std::tuple<int, int, uint32_t>, std::unique_ptr<FamilyEntry>> g_families;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -186,6 +194,10 @@ bool check_family(const cr_family *fam, std::string &err) {
     }
     if (fam->policy < CR_POLICY_DEPTH_FIRST || fam->policy > CR_POLICY_LEARNED) {
         err = "unknown policy";
+        return false;
+    }
+    if (fam->launch < 0 || fam->launch > 2) {
+        err = "unknown launch mode";
         return false;
     }
     if (fam->policy != CR_POLICY_DEPTH_FIRST && fam->engine == 2) {
@@ -275,6 +287,546 @@ bool plan_learned(const Family &F, std::vector<ItemSetup> &items, std::vector<cr
     });
     fallbacks = fb.load();
     return true;
+}
+
+// ------------------------------------------------------------------ batch execution
+struct Outputs {
+    uint64_t *frob, *frob_scaled;
+    int32_t *col_pole, *col_prec;
+    int64_t *lpoly;
+};
+
+// Per-call data shared by the sub-batches.
+struct BatchCtx {
+    const cr_family *fam = nullptr;
+    FamilyEntry *fe = nullptr;
+    const Family *F = nullptr;
+    DevFamily df{};
+    int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
+    bool want_mfma = false, use_bins = false;
+    hipStream_t stream = nullptr;
+    const int32_t *primes = nullptr;
+    const uint32_t *coeffs = nullptr;
+    Outputs out{};
+    bool init(const cr_family *f, const int32_t *pr, const uint32_t *co, hipStream_t s, std::string &err) {
+        fam = f;
+        primes = pr;
+        coeffs = co;
+        stream = s;
+        fe = get_family(f, err);
+        if (!fe) return false;
+        F = &fe->fam;
+        int32_t nco_, s_dim, b_;
+        cr_query_dims(f->nvars, f->degree, &nco_, &s_dim, &b_);
+        nco = nco_;
+        b = b_;
+        sdim = F->g.count;
+        df.nv = F->nv;
+        df.n = F->n;
+        df.d = F->d;
+        df.smask = F->smask;
+        df.s = F->g.count;
+        df.T = F->tgt.count;
+        df.nsrc = F->nsrc;
+        df.F = F->fin.count;
+        df.ndir = F->dirs.count;
+        df.nfinU = F->finU.count;
+        policy = f->policy;
+        want_mfma = (f->engine == 0 || f->engine == 2) && mfma_shape(df, nrt, nkb);
+        // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
+        use_bins = f->engine == 0 && fe->bl_ok;
+        return true;
+    }
+};
+
+struct SubBatch {
+    std::vector<int> idx;  // caller item indices
+    int arena = 0;
+    std::vector<ItemSetup> items;
+    std::vector<ItemPlan> plans;
+    std::vector<cr_status> st;
+    std::vector<std::string> errs;
+    std::vector<DigitParams> dps;
+    std::vector<char> digit_ok;
+    std::vector<int> live;  // local indices of the items that reach the device
+    bool use_mfma = false, use_bins = false;
+    int ct = 32, nphase = 0, fallbacks = 0;
+    struct Launch {
+        int phase, key, tile0, ntiles;
+    };
+    std::vector<Launch> launches;
+    std::vector<size_t> comb_first, comb_count;
+    size_t h_end = 0, o_items = 0, o_tiles = 0, o_ditems = 0, o_tables = 0, o_cu = 0, o_cg = 0, o_cp = 0, o_vx = 0;
+    size_t o_comb = 0, o_msrc = 0, o_malpha = 0, o_err = 0, o_Y = 0, o_hbuf = 0, o_store = 0, o_queue = 0;
+    DevFamily df{};
+    hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr, edone = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
+    double setup_ms = 0, finish_ms = 0;
+    float dev_ms = 0, red_ms = 0, asm_ms = 0, comb_ms = 0;
+    void destroy_events() {
+        for (hipEvent_t *e : {&e0, &em, &e1, &edone})
+            if (*e) {
+                (void)hipEventDestroy(*e);
+                *e = nullptr;
+            }
+        for (auto &ce : cev) {
+            (void)hipEventDestroy(ce.first);
+            (void)hipEventDestroy(ce.second);
+        }
+        cev.clear();
+    }
+};
+
+// Host setup, plans and the packed device image of one sub-batch (in the
+// pinned host half of its arena).
+cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
+    auto t0 = std::chrono::steady_clock::now();
+    const Family &F = *ctx.F;
+    const cr_family *fam = ctx.fam;
+    const int count = (int)sb.idx.size(), b = ctx.b, nrt = ctx.nrt, nkb = ctx.nkb, policy = ctx.policy;
+    sb.items.assign(count, ItemSetup());
+    sb.plans.assign(count, ItemPlan());
+    sb.st.assign(count, CR_OK);
+    sb.errs.assign(count, std::string());
+    sb.dps.assign(count, DigitParams());
+    sb.digit_ok.assign(count, 0);
+    parallel_for(count, [&](int i) {
+        const int g = sb.idx[i];
+        sb.st[i] = setup_item(F, ctx.primes[g], ctx.coeffs + (size_t)g * ctx.nco, fam->r, fam->n_series,
+                              sb.items[i], sb.errs[i]);
+        if (sb.st[i] == CR_OK && sb.items[i].b != b) {
+            sb.st[i] = CR_ESELFCHECK;
+            sb.errs[i] = "basis size differs from the Hodge numbers";
+        }
+        if (sb.st[i] == CR_OK && policy != CR_POLICY_LEARNED &&
+            !plan_item(F, sb.items[i], policy, sb.plans[i], sb.errs[i]))
+            sb.st[i] = CR_EINVAL;
+        if (sb.st[i] == CR_OK && ctx.want_mfma) {
+            ItemSetup &it = sb.items[i];
+            int umax = 0;
+            for (size_t k = 0; k < it.chain_u.size(); k++) umax = std::max<int>(umax, it.chain_u[k]);
+            const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
+            if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, sb.dps[i]) &&
+                mfma_supports_digits(sb.dps[i].D)) {
+                it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
+                pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), ctx.use_bins ? &ctx.fe->bl : nullptr);
+                sb.digit_ok[i] = 1;
+            }
+        }
+    });
+    if (policy == CR_POLICY_LEARNED &&
+        !plan_learned(F, sb.items, sb.st, sb.errs, sb.plans, fam->mlp, ctx.stream, sb.fallbacks, msg))
+        return CR_EDEVICE;
+    sb.live.clear();
+    for (int i = 0; i < count; i++)
+        if (sb.st[i] == CR_OK) sb.live.push_back(i);
+    const int nlive = (int)sb.live.size();
+    sb.df = ctx.df;
+    DevFamily &df = sb.df;
+    sb.use_bins = ctx.use_bins;
+    sb.use_mfma = ctx.want_mfma;
+    for (int li = 0; li < nlive && sb.use_mfma; li++) sb.use_mfma = sb.digit_ok[sb.live[li]] != 0;
+    for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
+        if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
+    if (sb.use_mfma && !sb.use_bins && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
+    sb.ct = 32;
+    if (!sb.use_mfma) {
+        while (sb.ct > 1 && reduce_lds_bytes(df, sb.ct) > 64 * 1024) sb.ct /= 2;
+        if (reduce_lds_bytes(df, sb.ct) > 64 * 1024) {
+            msg = "family too large for the LDS tile";
+            return CR_EINVAL;
+        }
+    }
+    sb.launches.clear();
+    sb.nphase = 0;
+    if (nlive == 0) {
+        sb.setup_ms = ms_since(t0);
+        return CR_OK;
+    }
+    const int ct = sb.ct;
+
+    // ---- vectors of every phase in launch order (phase, digit group, item), tiles of ct vectors of one item
+    std::vector<int> gkey(nlive, 0), dvals;
+    for (int li = 0; li < nlive; li++)
+        if (sb.use_mfma) gkey[li] = sb.dps[sb.live[li]].D + 100 * sb.dps[sb.live[li]].z32;
+    dvals = gkey;
+    std::sort(dvals.begin(), dvals.end());
+    dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
+    for (int li = 0; li < nlive; li++) sb.nphase = std::max(sb.nphase, (int)sb.plans[sb.live[li]].phase.size());
+    const int nphase = sb.nphase;
+    std::vector<DevTile> tiles;
+    std::vector<std::vector<size_t>> vec0(nlive, std::vector<size_t>(nphase, 0));
+    size_t nvec = 0;
+    for (int t = 0; t < nphase; t++)
+        for (int key : dvals) {
+            const int first = (int)tiles.size();
+            for (int li = 0; li < nlive; li++) {
+                const ItemPlan &pl = sb.plans[sb.live[li]];
+                if (gkey[li] != key || t >= (int)pl.phase.size()) continue;
+                const auto &ph = pl.phase[t];
+                vec0[li][t] = nvec;
+                for (int c0 = 0; c0 < (int)ph.size(); c0 += ct) {
+                    DevTile tl{};
+                    tl.item = li;
+                    tl.count = std::min(ct, (int)ph.size() - c0);
+                    tl.chain0 = (int32_t)(nvec + c0);
+                    tl.steps = ph[c0].pole - ph[c0].pend;
+                    tiles.push_back(tl);
+                }
+                nvec += ph.size();
+            }
+            // longest tiles first, so that the last wave of workgroups is short
+            std::stable_sort(tiles.begin() + first, tiles.end(),
+                             [](const DevTile &x, const DevTile &y) { return x.steps > y.steps; });
+            if ((int)tiles.size() > first) sb.launches.push_back({t, key, first, (int)tiles.size() - first});
+        }
+    std::vector<int32_t> row0(nlive, 0);
+    std::vector<size_t> coef0(nlive, 0), fin0(nlive, 0), apack_off(nlive, 0);
+    size_t nrows = 0, ncomb = 0, nmem = 0, nfin_all = 0, ncoef = 0;
+    for (int li = 0; li < nlive; li++) {
+        const ItemPlan &pl = sb.plans[sb.live[li]];
+        row0[li] = (int32_t)nrows;
+        nrows += pl.nrows;
+        for (auto &cb : pl.comb) ncomb += cb.size();
+        nmem += pl.msrc.size();
+        fin0[li] = nfin_all;
+        for (auto &ph : pl.phase)
+            for (auto &v : ph) nfin_all += v.out < 0;
+        coef0[li] = ncoef;
+        ncoef += (size_t)(sb.items[sb.live[li]].nchain() + b) * b;
+    }
+    if (nvec >= (size_t)INT32_MAX || nrows >= (size_t)INT32_MAX / 2) {
+        msg = "batch too large for 32-bit vector indices";
+        return CR_ENOMEM;
+    }
+
+    // ---- device layout
+    const size_t psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
+    const int sdim = ctx.sdim;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    FamilyEntry *fe = ctx.fe;
+    sb.o_tables = take(fe->tables.size());
+    sb.o_items = take(sizeof(DevItem) * nlive);
+    sb.o_tiles = take(sizeof(DevTile) * std::max<size_t>(tiles.size(), 1));
+    const size_t o_psi = take(sb.use_mfma ? 0 : 8 * psi_len * nlive);
+    if (sb.use_mfma) {
+        sb.o_ditems = take(sizeof(DevDigitItem) * nlive);
+        for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
+    }
+    const size_t o_rho = take(8 * rho_len * nlive);
+    const size_t o_coef = take(8 * ncoef);
+    sb.o_cu = take(2 * (size_t)F.nv * nvec);
+    sb.o_cg = take(4 * nvec);
+    sb.o_cp = take(4 * nvec);
+    sb.o_vx = take(sizeof(DevVec) * nvec);
+    sb.o_comb = take(sizeof(DevComb) * std::max<size_t>(ncomb, 1));
+    sb.o_msrc = take(4 * std::max<size_t>(nmem, 1));
+    sb.o_malpha = take(8 * std::max<size_t>(nmem, 1));
+    const size_t o_fvec = take(4 * std::max<size_t>(nfin_all, 1));
+    const size_t o_frow = take(4 * std::max<size_t>(nfin_all, 1));
+    sb.o_err = take(4);
+    sb.h_end = off;  // everything above is uploaded
+    sb.o_queue = take(4 * std::max<size_t>(sb.launches.size(), 1));
+    sb.o_Y = take(8 * (size_t)b * b * nlive);
+    const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
+    sb.o_hbuf = take(8 * (size_t)F.fin.count * nvec);
+    sb.o_store = take(8 * (size_t)sdim * std::max<size_t>(nrows, 1));
+    const size_t d_end = off;
+    Arena &ar = g_arenas[sb.arena];
+    if (!ar.ensure(d_end, sb.o_Y + 8 * (size_t)b * b * nlive)) {
+        msg = "device or pinned host allocation failed";
+        return CR_ENOMEM;
+    }
+    unsigned char *hb = static_cast<unsigned char *>(ar.host);
+    unsigned char *db = static_cast<unsigned char *>(ar.dev);
+    std::memcpy(hb + sb.o_tables, fe->tables.data(), fe->tables.size());
+    df.colmap = reinterpret_cast<const int16_t *>(db + sb.o_tables + fe->off_colmap);
+    df.gsrc = reinterpret_cast<const int16_t *>(db + sb.o_tables + fe->off_gsrc);
+    df.gw = reinterpret_cast<const int16_t *>(db + sb.o_tables + fe->off_gw);
+    df.finmap = reinterpret_cast<const int16_t *>(db + sb.o_tables + fe->off_finmap);
+    df.dirs = reinterpret_cast<const int8_t *>(db + sb.o_tables + fe->off_dirs);
+    df.finU = reinterpret_cast<const int8_t *>(db + sb.o_tables + fe->off_finU);
+    DevItem *hitems = reinterpret_cast<DevItem *>(hb + sb.o_items);
+    int16_t *hcu = reinterpret_cast<int16_t *>(hb + sb.o_cu);
+    int32_t *hcg = reinterpret_cast<int32_t *>(hb + sb.o_cg);
+    int32_t *hcp = reinterpret_cast<int32_t *>(hb + sb.o_cp);
+    DevVec *hvx = reinterpret_cast<DevVec *>(hb + sb.o_vx);
+    DevComb *hcomb = reinterpret_cast<DevComb *>(hb + sb.o_comb);
+    int32_t *hmsrc = reinterpret_cast<int32_t *>(hb + sb.o_msrc);
+    uint64_t *hmal = reinterpret_cast<uint64_t *>(hb + sb.o_malpha);
+    int32_t *hfvec = reinterpret_cast<int32_t *>(hb + o_fvec);
+    int32_t *hfrow = reinterpret_cast<int32_t *>(hb + o_frow);
+    // combine entries grouped by the phase that reads them
+    sb.comb_first.assign(nphase + 1, 0);
+    sb.comb_count.assign(nphase + 1, 0);
+    {
+        size_t at = 0, mat = 0;
+        for (int t = 1; t < nphase; t++) {
+            sb.comb_first[t] = at;
+            for (int li = 0; li < nlive; li++) {
+                const ItemPlan &pl = sb.plans[sb.live[li]];
+                if (t >= (int)pl.comb.size()) continue;
+                for (const PlanComb &pc : pl.comb[t]) {
+                    DevComb &dc = hcomb[at++];
+                    dc.row = row0[li] + pc.row;
+                    dc.item = li;
+                    dc.m0 = (int32_t)mat;
+                    for (int j = pc.m0; j < pc.m1; j++) {
+                        const int32_t src = pl.msrc[j];
+                        hmsrc[mat] = src >= 0 ? row0[li] + src : src;
+                        hmal[mat] = pl.malpha[j];
+                        mat++;
+                    }
+                    dc.m1 = (int32_t)mat;
+                }
+            }
+            sb.comb_count[t] = at - sb.comb_first[t];
+        }
+    }
+    parallel_for(nlive, [&](int li) {
+        const ItemSetup &it = sb.items[sb.live[li]];
+        const ItemPlan &pl = sb.plans[sb.live[li]];
+        DevItem &di = hitems[li];
+        std::memset(&di, 0, sizeof(di));
+        di.q = it.mq.q;
+        di.mu = it.mq.mu;
+        di.sbits = it.mq.sbits;
+        di.b = b;
+        di.nchain = it.nchain();
+        di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
+        di.rho = reinterpret_cast<const uint64_t *>(db + o_rho) + rho_len * li;
+        di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + coef0[li];
+        di.Y = reinterpret_cast<uint64_t *>(db + sb.o_Y) + (size_t)b * b * li;
+        di.H = reinterpret_cast<uint64_t *>(db + o_H) + (size_t)F.fin.count * b * li;
+        uint64_t *hc = reinterpret_cast<uint64_t *>(hb + o_coef) + coef0[li];
+        std::memcpy(hc, it.coef.data(), 8 * it.coef.size());
+        std::memset(hc + it.coef.size(), 0, 8 * (size_t)b * b);
+        for (int c = 0; c < b; c++) hc[it.coef.size() + (size_t)c * b + c] = 1;
+        di.fvec = reinterpret_cast<const int32_t *>(db + o_fvec) + fin0[li];
+        di.frow = reinterpret_cast<const int32_t *>(db + o_frow) + fin0[li];
+        int nfin = 0;
+        for (int t = 0; t < (int)pl.phase.size(); t++) {
+            const auto &ph = pl.phase[t];
+            for (size_t k = 0; k < ph.size(); k++) {
+                const PlanVec &pv = ph[k];
+                const size_t g = vec0[li][t] + k;
+                for (int i = 0; i < F.nv; i++) hcu[g * F.nv + i] = pv.u[i];
+                hcg[g] = pv.gamma;
+                hcp[g] = pv.pole;
+                hvx[g].pend = pv.pend;
+                hvx[g].in = pv.in >= 0 ? row0[li] + pv.in : -1;
+                hvx[g].out = pv.out >= 0 ? row0[li] + pv.out : -1;
+                hvx[g].dir = pv.dir;
+                if (pv.out < 0) {
+                    hfvec[fin0[li] + nfin] = (int32_t)g;
+                    hfrow[fin0[li] + nfin] = pv.crow;
+                    nfin++;
+                }
+            }
+        }
+        di.nfin = nfin;
+        if (sb.use_mfma) {
+            const DigitParams &dp = sb.dps[sb.live[li]];
+            DevDigitItem &dd = reinterpret_cast<DevDigitItem *>(hb + sb.o_ditems)[li];
+            dd.Bd = dp.Bd;
+            dd.Qd = dp.Qd;
+            dd.invQ = dp.invQ;
+            dd.BHd = dp.BHd;
+            dd.invBH = dp.invBH;
+            dd.Bh = dp.Bh;
+            dd.Bsplit = dp.Bsplit;
+            dd.invBsplit = dp.invBsplit;
+            dd.bias = dp.bias;
+            dd.Qp = dp.Qp;
+            dd.q = it.mq.q;
+            dd.magic = dp.magic;
+            dd.shift = dp.shift;
+            dd.B = dp.B;
+            dd.halfB = dp.halfB;
+            dd.D = dp.D;
+            dd.h = dp.h;
+            dd.ds = dp.ds;
+            dd.z32 = dp.z32;
+            dd.chain0 = 0;
+            dd.nchain = it.nchain();
+            dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
+            std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
+        } else {
+            std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
+        }
+        std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
+    });
+    std::memcpy(hb + sb.o_tiles, tiles.data(), sizeof(DevTile) * tiles.size());
+    std::memset(hb + sb.o_err, 0, 4);
+    sb.setup_ms = ms_since(t0);
+    return CR_OK;
+}
+
+// Upload, per phase the combines it reads and its reductions, the assembly,
+// and the download of Y and the error flags -- all asynchronous on the stream.
+cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
+    if (sb.live.empty()) return CR_OK;
+    hipStream_t stream = ctx.stream;
+    Arena &ar = g_arenas[sb.arena];
+    unsigned char *hb = static_cast<unsigned char *>(ar.host);
+    unsigned char *db = static_cast<unsigned char *>(ar.dev);
+    const DevFamily &df = sb.df;
+    const int nlive = (int)sb.live.size(), b = ctx.b;
+    (void)hipEventCreate(&sb.e0);
+    (void)hipEventCreate(&sb.e1);
+    (void)hipEventCreate(&sb.em);
+    (void)hipEventCreateWithFlags(&sb.edone, hipEventDisableTiming);
+    hipError_t he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
+    (void)hipEventRecord(sb.e0, stream);
+    const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + sb.o_items);
+    const int16_t *cu = reinterpret_cast<const int16_t *>(db + sb.o_cu);
+    const int32_t *cgp = reinterpret_cast<const int32_t *>(db + sb.o_cg);
+    const int32_t *cp = reinterpret_cast<const int32_t *>(db + sb.o_cp);
+    const DevVec *vxp = reinterpret_cast<const DevVec *>(db + sb.o_vx);
+    uint64_t *storep = reinterpret_cast<uint64_t *>(db + sb.o_store);
+    uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + sb.o_hbuf);
+    int *errp = reinterpret_cast<int *>(db + sb.o_err);
+    const int mode = sb.use_mfma && sb.use_bins ? ctx.fam->launch : 0;
+    int *queue = reinterpret_cast<int *>(db + sb.o_queue);
+    // the reduction phases (and the combines between them) on stream `rs`
+    auto reductions = [&](hipStream_t rs, bool timed) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (mode > 0) e = launch_zero_ints(queue, (int)sb.launches.size(), rs);
+        for (int t = 0; t < sb.nphase && e == hipSuccess; t++) {
+            if (t > 0 && sb.comb_count[t] > 0) {
+                hipEvent_t a = nullptr, z = nullptr;
+                if (timed) {
+                    (void)hipEventCreate(&a);
+                    (void)hipEventCreate(&z);
+                    (void)hipEventRecord(a, rs);
+                }
+                e = launch_combine(ditems_v, reinterpret_cast<const DevComb *>(db + sb.o_comb) + sb.comb_first[t],
+                                   (int)sb.comb_count[t], reinterpret_cast<const int32_t *>(db + sb.o_msrc),
+                                   reinterpret_cast<const uint64_t *>(db + sb.o_malpha), storep, ctx.sdim, rs);
+                if (timed) {
+                    (void)hipEventRecord(z, rs);
+                    sb.cev.push_back({a, z});
+                }
+            }
+            for (size_t li = 0; li < sb.launches.size(); li++) {
+                const SubBatch::Launch &L = sb.launches[li];
+                if (L.phase != t || e != hipSuccess) continue;
+                const DevTile *gt = reinterpret_cast<const DevTile *>(db + sb.o_tiles) + L.tile0;
+                if (sb.use_mfma) {
+                    const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems);
+                    const int Dg = L.key % 100;
+                    const bool z32g = L.key >= 100;
+                    if (sb.use_bins)
+                        e = launch_reduce_mfma4(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
+                                                reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
+                                                errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
+                    else
+                        e = launch_reduce_mfma(df, ditems, gt, L.ntiles, cu, cgp, cp, hb64, errp, Dg, rs);
+                } else {
+                    e = launch_reduce(df, ditems_v, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64, sb.ct, errp, rs);
+                }
+            }
+        }
+        return e;
+    };
+    if (he == hipSuccess && mode == 2) {
+        // signature of every launch parameter: an identical one replays the cached graph
+        std::string sig = std::to_string((uintptr_t)db) + ":" + std::to_string(sb.nphase);
+        for (auto &L : sb.launches)
+            sig += "|" + std::to_string(L.phase) + "," + std::to_string(L.key) + "," + std::to_string(L.tile0) + "," +
+                   std::to_string(L.ntiles);
+        for (int t = 0; t < sb.nphase; t++) sig += "/" + std::to_string(sb.comb_first[t]) + "," + std::to_string(sb.comb_count[t]);
+        for (size_t o : {sb.o_items, sb.o_tiles, sb.o_ditems, sb.o_tables, sb.o_cu, sb.o_cg, sb.o_cp, sb.o_vx,
+                         sb.o_comb, sb.o_msrc, sb.o_malpha, sb.o_err, sb.o_hbuf, sb.o_store, sb.o_queue})
+            sig += ";" + std::to_string(o);
+        hipGraphExec_t exec = nullptr;
+        auto f = g_graphs.find(sig);
+        if (f != g_graphs.end()) {
+            exec = f->second;
+        } else {
+            if (!g_capture) he = hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking);
+            hipGraph_t graph = nullptr;
+            if (he == hipSuccess) he = hipStreamBeginCapture(g_capture, hipStreamCaptureModeRelaxed);
+            if (he == hipSuccess) {
+                hipError_t ec = reductions(g_capture, false);
+                he = hipStreamEndCapture(g_capture, &graph);
+                if (he == hipSuccess) he = ec;
+            }
+            if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (he == hipSuccess) {
+                if (g_graphs.size() >= 16) clear_graphs();
+                g_graphs.emplace(sig, exec);
+            }
+        }
+        if (he == hipSuccess) he = hipGraphLaunch(exec, stream);
+    } else if (he == hipSuccess) {
+        he = reductions(stream, true);
+    }
+    (void)hipEventRecord(sb.em, stream);
+    if (he == hipSuccess) he = launch_assemble(df, ditems_v, nlive, hb64, stream);
+    (void)hipEventRecord(sb.e1, stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(hb + sb.o_Y, db + sb.o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(hb + sb.o_err, db + sb.o_err, 4, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipEventRecord(sb.edone, stream);
+    if (he != hipSuccess) {
+        msg = std::string("HIP error: ") + hipGetErrorString(he);
+        return CR_EDEVICE;
+    }
+    return CR_OK;
+}
+
+// Waits for the sub-batch, then unscales and recovers Q(T) of its items.
+cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, std::vector<std::string> &errs,
+                       std::string &msg) {
+    const int count = (int)sb.idx.size(), b = ctx.b;
+    for (int i = 0; i < count; i++) {
+        st[sb.idx[i]] = sb.st[i];
+        errs[sb.idx[i]] = sb.errs[i];
+    }
+    if (sb.live.empty()) return CR_OK;
+    // edone follows the downloads of this sub-batch only (later sub-batches may still run)
+    hipError_t he = hipEventSynchronize(sb.edone);
+    if (he == hipSuccess) {
+        (void)hipEventElapsedTime(&sb.dev_ms, sb.e0, sb.e1);
+        (void)hipEventElapsedTime(&sb.red_ms, sb.e0, sb.em);
+        (void)hipEventElapsedTime(&sb.asm_ms, sb.em, sb.e1);
+        for (auto &ce : sb.cev) {
+            float x = 0;
+            (void)hipEventElapsedTime(&x, ce.first, ce.second);
+            sb.comb_ms += x;
+        }
+    }
+    sb.destroy_events();
+    if (he != hipSuccess) {
+        msg = std::string("HIP error: ") + hipGetErrorString(he);
+        return CR_EDEVICE;
+    }
+    unsigned char *hb = static_cast<unsigned char *>(g_arenas[sb.arena].host);
+    int derr;
+    std::memcpy(&derr, hb + sb.o_err, 4);
+    if (derr) {
+        msg = "device reduction invariant violated (code " + std::to_string(derr) + ")";
+        return CR_ESELFCHECK;
+    }
+    auto t2 = std::chrono::steady_clock::now();
+    const uint64_t *Yh = reinterpret_cast<const uint64_t *>(hb + sb.o_Y);
+    const Outputs &o = ctx.out;
+    parallel_for((int)sb.live.size(), [&](int li) {
+        const int i = sb.live[li], g = sb.idx[i];
+        const size_t bb = (size_t)b * b;
+        st[g] = finish_item(*ctx.F, sb.items[i], Yh + bb * li, o.frob + bb * g, o.col_pole + (size_t)b * g,
+                            o.col_prec + (size_t)b * g, o.lpoly + (size_t)4 * (b + 1) * g, errs[g]);
+        if (o.frob_scaled) std::memcpy(o.frob_scaled + bb * g, Yh + bb * li, 8 * bb);
+    });
+    sb.finish_ms = ms_since(t2);
+    return CR_OK;
 }
 
 }  // namespace
@@ -405,7 +957,9 @@ cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs
 
 cr_status cr_release(void) {
     std::lock_guard<std::mutex> lk(g_mutex);
-    g_arena.release();
+    clear_graphs();
+    g_arenas[0].release();
+    g_arenas[1].release();
     return CR_OK;
 }
 
@@ -417,398 +971,38 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     if (count < 0 || (count > 0 && (!primes || !coeffs || !frob || !col_pole || !col_prec || !lpoly)))
         return fail(CR_EINVAL, "null output or input pointer");
     if (count == 0) return CR_OK;
+    if (fam->policy == CR_POLICY_LEARNED && !fam->mlp) return fail(CR_EINVAL, "CR_POLICY_LEARNED needs a model (cr_family.mlp)");
     std::lock_guard<std::mutex> lk(g_mutex);
-    FamilyEntry *fe = get_family(fam, err);
-    if (!fe) return fail(CR_EINVAL, err);
-    const Family &F = fe->fam;
-    int32_t nco, s_dim, b;
-    cr_query_dims(fam->nvars, fam->degree, &nco, &s_dim, &b);
-    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    auto t0 = std::chrono::steady_clock::now();
-
-    // ---- host setup and reduction plan, one item per task
-    DevFamily df{};
-    df.nv = F.nv;
-    df.n = F.n;
-    df.d = F.d;
-    df.smask = F.smask;
-    df.s = F.g.count;
-    df.T = F.tgt.count;
-    df.nsrc = F.nsrc;
-    df.F = F.fin.count;
-    df.ndir = F.dirs.count;
-    df.nfinU = F.finU.count;
-    const int policy = fam->policy;
-    int nrt = 0, nkb = 0;
-    const bool want_mfma = (fam->engine == 0 || fam->engine == 2) && mfma_shape(df, nrt, nkb);
-    // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
-    const bool use_bins = fam->engine == 0 && fe->bl_ok;
-    std::vector<ItemSetup> items(count);
-    std::vector<ItemPlan> plans(count);
+    BatchCtx ctx;
+    if (!ctx.init(fam, primes, coeffs, reinterpret_cast<hipStream_t>(hip_stream), err)) return fail(CR_EINVAL, err);
+    ctx.out = {frob, frob_scaled, col_pole, col_prec, lpoly};
+    // Sub-batches: the host prepares sub-batch k + 1 while the device reduces sub-batch k.
+    const int S = count >= 128 ? 4 : (count >= 48 ? 2 : 1);
+    std::vector<SubBatch> sub(S);
+    for (int k = 0; k < S; k++) {
+        const int a = (int)((int64_t)count * k / S), z = (int)((int64_t)count * (k + 1) / S);
+        for (int i = a; i < z; i++) sub[k].idx.push_back(i);
+        sub[k].arena = k & 1;
+    }
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
-    std::vector<DigitParams> dps(count);
-    std::vector<char> digit_ok(count, 0);
-    parallel_for(count, [&](int i) {
-        st[i] = setup_item(F, primes[i], coeffs + (size_t)i * nco, fam->r, fam->n_series, items[i], errs[i]);
-        if (st[i] == CR_OK && items[i].b != b) {
-            st[i] = CR_ESELFCHECK;
-            errs[i] = "basis size differs from the Hodge numbers";
-        }
-        if (st[i] == CR_OK && policy != CR_POLICY_LEARNED && !plan_item(F, items[i], policy, plans[i], errs[i]))
-            st[i] = CR_EINVAL;
-        if (st[i] == CR_OK && want_mfma) {
-            ItemSetup &it = items[i];
-            int umax = 0;
-            for (size_t k = 0; k < it.chain_u.size(); k++) umax = std::max<int>(umax, it.chain_u[k]);
-            const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
-            if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, dps[i]) && mfma_supports_digits(dps[i].D)) {
-                it.apack.resize((size_t)nrt * dps[i].D * nkb * 1024);
-                pack_psi_digits(F, it, dps[i], nrt, nkb, it.apack.data(), use_bins ? &fe->bl : nullptr);
-                digit_ok[i] = 1;
-            }
-        }
-    });
-    int fallbacks = 0;
-    if (policy == CR_POLICY_LEARNED) {
-        if (!fam->mlp) return fail(CR_EINVAL, "CR_POLICY_LEARNED needs a model (cr_family.mlp)");
-        std::string lerr;
-        if (!plan_learned(F, items, st, errs, plans, fam->mlp, stream, fallbacks, lerr)) return fail(CR_EDEVICE, lerr);
-    }
-    const double setup_ms = ms_since(t0);
-
-    std::vector<int> live;
-    for (int i = 0; i < count; i++)
-        if (st[i] == CR_OK) live.push_back(i);
-    const int nlive = (int)live.size();
-    if (nlive == 0) {
-        cr_status first = CR_OK;
-        for (int i = 0; i < count; i++) {
-            if (item_status) item_status[i] = st[i];
-            if (first == CR_OK) {
-                first = st[i];
-                g_err = "item " + std::to_string(i) + ": " + errs[i];
-            }
-        }
-        if (stats) {
-            std::memset(stats, 0, sizeof(*stats));
-            stats->setup_ms = setup_ms;
-            stats->policy = policy;
-        }
-        return first;
-    }
-    bool use_mfma = want_mfma;
-    for (int li = 0; li < nlive && use_mfma; li++) use_mfma = digit_ok[live[li]] != 0;
-    for (int li = 0; li < nlive && use_mfma && use_bins; li++)
-        if (!mfma4_supports(df, dps[live[li]].D)) use_mfma = false;  // packed for the other layout: fall back
-    if (use_mfma && !use_bins && policy != CR_POLICY_DEPTH_FIRST) use_mfma = false;
-    int ct = 32;
-    if (!use_mfma) {
-        while (ct > 1 && reduce_lds_bytes(df, ct) > 64 * 1024) ct /= 2;
-        if (reduce_lds_bytes(df, ct) > 64 * 1024) return fail(CR_EINVAL, "family too large for the LDS tile");
-    }
-
-    // ---- vectors of every phase in launch order (phase, digit group, item), tiles of ct vectors of one item
-    std::vector<int> gkey(nlive, 0), dvals;
-    for (int li = 0; li < nlive; li++)
-        if (use_mfma) gkey[li] = dps[live[li]].D + 100 * dps[live[li]].z32;
-    dvals = gkey;
-    std::sort(dvals.begin(), dvals.end());
-    dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
-    int nphase = 0;
-    for (int i : live) nphase = std::max(nphase, (int)plans[i].phase.size());
-    struct Launch {
-        int phase, key, tile0, ntiles;
+    cr_status fatal = CR_OK;
+    std::string fatal_msg;
+    auto stop_all = [&](int upto) {  // drain the device before reporting a failure
+        (void)hipStreamSynchronize(ctx.stream);
+        for (int k = 0; k <= upto && k < S; k++) sub[k].destroy_events();
     };
-    std::vector<Launch> launches;
-    std::vector<DevTile> tiles;
-    std::vector<std::vector<size_t>> vec0(nlive, std::vector<size_t>(nphase, 0));
-    size_t nvec = 0;
-    for (int t = 0; t < nphase; t++)
-        for (int key : dvals) {
-            const int first = (int)tiles.size();
-            for (int li = 0; li < nlive; li++) {
-                const ItemPlan &pl = plans[live[li]];
-                if (gkey[li] != key || t >= (int)pl.phase.size()) continue;
-                const auto &ph = pl.phase[t];
-                vec0[li][t] = nvec;
-                for (int c0 = 0; c0 < (int)ph.size(); c0 += ct) {
-                    DevTile tl{};
-                    tl.item = li;
-                    tl.count = std::min(ct, (int)ph.size() - c0);
-                    tl.chain0 = (int32_t)(nvec + c0);
-                    tl.steps = ph[c0].pole - ph[c0].pend;
-                    tiles.push_back(tl);
-                }
-                nvec += ph.size();
-            }
-            if ((int)tiles.size() > first) launches.push_back({t, key, first, (int)tiles.size() - first});
-        }
-    std::vector<int32_t> row0(nlive, 0);
-    size_t nrows = 0, ncomb = 0, nmem = 0, nfin_all = 0, ncoef = 0;
-    for (int li = 0; li < nlive; li++) {
-        const ItemPlan &pl = plans[live[li]];
-        row0[li] = (int32_t)nrows;
-        nrows += pl.nrows;
-        for (auto &cb : pl.comb) ncomb += cb.size();
-        nmem += pl.msrc.size();
-        for (auto &ph : pl.phase)
-            for (auto &v : ph) nfin_all += v.out < 0;
-        ncoef += (size_t)(items[live[li]].nchain() + b) * b;
+    for (int k = 0; k < S && fatal == CR_OK; k++) {
+        fatal = prepare_sub(ctx, sub[k], fatal_msg);
+        if (fatal == CR_OK) fatal = launch_sub(ctx, sub[k], fatal_msg);
+        if (fatal == CR_OK && k > 0) fatal = complete_sub(ctx, sub[k - 1], st, errs, fatal_msg);
+        if (fatal != CR_OK) stop_all(k);
     }
-    if (nvec >= (size_t)INT32_MAX || nrows >= (size_t)INT32_MAX / 2)
-        return fail(CR_ENOMEM, "batch too large for 32-bit vector indices");
-
-    // ---- device layout
-    const size_t psi_len = (size_t)F.nsrc * F.tgt.count, rho_len = (size_t)b * F.fin.count;
-    const int sdim = F.g.count;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = off;
-        off = align256(off + bytes);
-        return at;
-    };
-    const size_t o_tables = take(fe->tables.size());
-    const size_t o_items = take(sizeof(DevItem) * std::max(nlive, 1));
-    const size_t o_tiles = take(sizeof(DevTile) * std::max<size_t>(tiles.size(), 1));
-    const size_t o_psi = take(use_mfma ? 0 : 8 * psi_len * nlive);
-    std::vector<size_t> apack_off(nlive, 0);
-    size_t o_ditems = 0;
-    if (use_mfma) {
-        o_ditems = take(sizeof(DevDigitItem) * nlive);
-        for (int li = 0; li < nlive; li++) apack_off[li] = take(items[live[li]].apack.size());
+    if (fatal == CR_OK) fatal = complete_sub(ctx, sub[S - 1], st, errs, fatal_msg);
+    if (fatal != CR_OK) {
+        stop_all(S - 1);
+        return fail(fatal, fatal_msg);
     }
-    const size_t o_rho = take(8 * rho_len * nlive);
-    const size_t o_coef = take(8 * ncoef);
-    const size_t o_cu = take(2 * (size_t)F.nv * nvec);
-    const size_t o_cg = take(4 * nvec);
-    const size_t o_cp = take(4 * nvec);
-    const size_t o_vx = take(sizeof(DevVec) * nvec);
-    const size_t o_comb = take(sizeof(DevComb) * std::max<size_t>(ncomb, 1));
-    const size_t o_msrc = take(4 * std::max<size_t>(nmem, 1));
-    const size_t o_malpha = take(8 * std::max<size_t>(nmem, 1));
-    const size_t o_fvec = take(4 * std::max<size_t>(nfin_all, 1));
-    const size_t o_frow = take(4 * std::max<size_t>(nfin_all, 1));
-    const size_t o_err = take(4);
-    const size_t h_end = off;  // everything above is uploaded
-    const size_t o_Y = take(8 * (size_t)b * b * nlive);
-    const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
-    const size_t o_hbuf = take(8 * (size_t)F.fin.count * nvec);
-    const size_t o_store = take(8 * (size_t)sdim * std::max<size_t>(nrows, 1));
-    const size_t d_end = off;
-    if (!g_arena.ensure(d_end, h_end + 8 * (size_t)b * b * nlive + 256))
-        return fail(CR_ENOMEM, "device or pinned host allocation failed");
-    unsigned char *hb = static_cast<unsigned char *>(g_arena.host);
-    unsigned char *db = static_cast<unsigned char *>(g_arena.dev);
-    std::memcpy(hb + o_tables, fe->tables.data(), fe->tables.size());
-    df.colmap = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_colmap);
-    df.gsrc = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_gsrc);
-    df.gw = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_gw);
-    df.finmap = reinterpret_cast<const int16_t *>(db + o_tables + fe->off_finmap);
-    df.dirs = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_dirs);
-    df.finU = reinterpret_cast<const int8_t *>(db + o_tables + fe->off_finU);
-    DevItem *hitems = reinterpret_cast<DevItem *>(hb + o_items);
-    int16_t *hcu = reinterpret_cast<int16_t *>(hb + o_cu);
-    int32_t *hcg = reinterpret_cast<int32_t *>(hb + o_cg);
-    int32_t *hcp = reinterpret_cast<int32_t *>(hb + o_cp);
-    DevVec *hvx = reinterpret_cast<DevVec *>(hb + o_vx);
-    DevComb *hcomb = reinterpret_cast<DevComb *>(hb + o_comb);
-    int32_t *hmsrc = reinterpret_cast<int32_t *>(hb + o_msrc);
-    uint64_t *hmal = reinterpret_cast<uint64_t *>(hb + o_malpha);
-    int32_t *hfvec = reinterpret_cast<int32_t *>(hb + o_fvec);
-    int32_t *hfrow = reinterpret_cast<int32_t *>(hb + o_frow);
-    // combine entries grouped by the phase that reads them
-    std::vector<size_t> comb_first(nphase + 1, 0), comb_count(nphase + 1, 0);
-    {
-        size_t at = 0, mat = 0;
-        for (int t = 1; t < nphase; t++) {
-            comb_first[t] = at;
-            for (int li = 0; li < nlive; li++) {
-                const ItemPlan &pl = plans[live[li]];
-                if (t >= (int)pl.comb.size()) continue;
-                for (const PlanComb &pc : pl.comb[t]) {
-                    DevComb &dc = hcomb[at++];
-                    dc.row = row0[li] + pc.row;
-                    dc.item = li;
-                    dc.m0 = (int32_t)mat;
-                    for (int j = pc.m0; j < pc.m1; j++) {
-                        const int32_t src = pl.msrc[j];
-                        hmsrc[mat] = src >= 0 ? row0[li] + src : src;
-                        hmal[mat] = pl.malpha[j];
-                        mat++;
-                    }
-                    dc.m1 = (int32_t)mat;
-                }
-            }
-            comb_count[t] = at - comb_first[t];
-        }
-    }
-    size_t coef_at = 0, fin_at = 0;
-    for (int li = 0; li < nlive; li++) {
-        const ItemSetup &it = items[live[li]];
-        const ItemPlan &pl = plans[live[li]];
-        DevItem &di = hitems[li];
-        std::memset(&di, 0, sizeof(di));
-        di.q = it.mq.q;
-        di.mu = it.mq.mu;
-        di.sbits = it.mq.sbits;
-        di.b = b;
-        di.nchain = it.nchain();
-        di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
-        di.rho = reinterpret_cast<const uint64_t *>(db + o_rho) + rho_len * li;
-        di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + coef_at;
-        di.Y = reinterpret_cast<uint64_t *>(db + o_Y) + (size_t)b * b * li;
-        di.H = reinterpret_cast<uint64_t *>(db + o_H) + (size_t)F.fin.count * b * li;
-        uint64_t *hc = reinterpret_cast<uint64_t *>(hb + o_coef) + coef_at;
-        std::memcpy(hc, it.coef.data(), 8 * it.coef.size());
-        std::memset(hc + it.coef.size(), 0, 8 * (size_t)b * b);
-        for (int c = 0; c < b; c++) hc[it.coef.size() + (size_t)c * b + c] = 1;
-        coef_at += (size_t)(it.nchain() + b) * b;
-        // vectors
-        di.fvec = reinterpret_cast<const int32_t *>(db + o_fvec) + fin_at;
-        di.frow = reinterpret_cast<const int32_t *>(db + o_frow) + fin_at;
-        int nfin = 0;
-        for (int t = 0; t < (int)pl.phase.size(); t++) {
-            const auto &ph = pl.phase[t];
-            for (size_t k = 0; k < ph.size(); k++) {
-                const PlanVec &pv = ph[k];
-                const size_t g = vec0[li][t] + k;
-                for (int i = 0; i < F.nv; i++) hcu[g * F.nv + i] = pv.u[i];
-                hcg[g] = pv.gamma;
-                hcp[g] = pv.pole;
-                hvx[g].pend = pv.pend;
-                hvx[g].in = pv.in >= 0 ? row0[li] + pv.in : -1;
-                hvx[g].out = pv.out >= 0 ? row0[li] + pv.out : -1;
-                hvx[g].dir = pv.dir;
-                if (pv.out < 0) {
-                    hfvec[fin_at + nfin] = (int32_t)g;
-                    hfrow[fin_at + nfin] = pv.crow;
-                    nfin++;
-                }
-            }
-        }
-        di.nfin = nfin;
-        fin_at += nfin;
-        if (use_mfma) {
-            const DigitParams &dp = dps[live[li]];
-            DevDigitItem &dd = reinterpret_cast<DevDigitItem *>(hb + o_ditems)[li];
-            dd.Bd = dp.Bd;
-            dd.Qd = dp.Qd;
-            dd.invQ = dp.invQ;
-            dd.BHd = dp.BHd;
-            dd.invBH = dp.invBH;
-            dd.Bh = dp.Bh;
-            dd.Bsplit = dp.Bsplit;
-            dd.invBsplit = dp.invBsplit;
-            dd.bias = dp.bias;
-            dd.Qp = dp.Qp;
-            dd.q = it.mq.q;
-            dd.magic = dp.magic;
-            dd.shift = dp.shift;
-            dd.B = dp.B;
-            dd.halfB = dp.halfB;
-            dd.D = dp.D;
-            dd.h = dp.h;
-            dd.ds = dp.ds;
-            dd.z32 = dp.z32;
-            dd.chain0 = 0;
-            dd.nchain = it.nchain();
-            dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
-            std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
-        } else {
-            std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
-        }
-        std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
-    }
-    std::memcpy(hb + o_tiles, tiles.data(), sizeof(DevTile) * tiles.size());
-    std::memset(hb + o_err, 0, 4);
-
-    // ---- device work: per phase the combines it reads, then its reductions; then the assembly
-    hipEvent_t e0, e1, em;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventCreate(&em);
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
-    hipError_t he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, stream);
-    (void)hipEventRecord(e0, stream);
-    const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + o_items);
-    const int16_t *cu = reinterpret_cast<const int16_t *>(db + o_cu);
-    const int32_t *cgp = reinterpret_cast<const int32_t *>(db + o_cg);
-    const int32_t *cp = reinterpret_cast<const int32_t *>(db + o_cp);
-    const DevVec *vxp = reinterpret_cast<const DevVec *>(db + o_vx);
-    uint64_t *storep = reinterpret_cast<uint64_t *>(db + o_store);
-    uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + o_hbuf);
-    int *errp = reinterpret_cast<int *>(db + o_err);
-    for (int t = 0; t < nphase && he == hipSuccess; t++) {
-        if (t > 0 && comb_count[t] > 0) {
-            hipEvent_t a, z;
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&z);
-            (void)hipEventRecord(a, stream);
-            he = launch_combine(ditems_v, reinterpret_cast<const DevComb *>(db + o_comb) + comb_first[t],
-                                (int)comb_count[t], reinterpret_cast<const int32_t *>(db + o_msrc),
-                                reinterpret_cast<const uint64_t *>(db + o_malpha), storep, sdim, stream);
-            (void)hipEventRecord(z, stream);
-            cev.push_back({a, z});
-        }
-        for (const Launch &L : launches) {
-            if (L.phase != t || he != hipSuccess) continue;
-            const DevTile *gt = reinterpret_cast<const DevTile *>(db + o_tiles) + L.tile0;
-            if (use_mfma) {
-                const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + o_ditems);
-                const int Dg = L.key % 100;
-                const bool z32g = L.key >= 100;
-                if (use_bins)
-                    he = launch_reduce_mfma4(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
-                                             reinterpret_cast<const uint32_t *>(db + o_tables + fe->off_slots), errp,
-                                             Dg, z32g, stream);
-                else
-                    he = launch_reduce_mfma(df, ditems, gt, L.ntiles, cu, cgp, cp, hb64, errp, Dg, stream);
-            } else {
-                he = launch_reduce(df, ditems_v, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64, ct, errp, stream);
-            }
-        }
-    }
-    (void)hipEventRecord(em, stream);
-    if (he == hipSuccess) he = launch_assemble(df, ditems_v, nlive, hb64, stream);
-    (void)hipEventRecord(e1, stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(hb + o_Y, db + o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(hb + o_err, db + o_err, 4, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(stream);
-    float dev_ms = 0, red_ms = 0, asm_ms = 0, comb_ms = 0;
-    if (he == hipSuccess) {
-        (void)hipEventElapsedTime(&dev_ms, e0, e1);
-        (void)hipEventElapsedTime(&red_ms, e0, em);
-        (void)hipEventElapsedTime(&asm_ms, em, e1);
-        for (auto &ce : cev) {
-            float x = 0;
-            (void)hipEventElapsedTime(&x, ce.first, ce.second);
-            comb_ms += x;
-        }
-    }
-    for (auto &ce : cev) {
-        (void)hipEventDestroy(ce.first);
-        (void)hipEventDestroy(ce.second);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(em);
-    if (he != hipSuccess) return fail(CR_EDEVICE, std::string("HIP error: ") + hipGetErrorString(he));
-    int derr;
-    std::memcpy(&derr, hb + o_err, 4);
-    if (derr) return fail(CR_ESELFCHECK, "device reduction invariant violated (code " + std::to_string(derr) + ")");
-
-    // ---- finish: unscale, Q(T)
-    auto t2 = std::chrono::steady_clock::now();
-    const uint64_t *Yh = reinterpret_cast<const uint64_t *>(hb + o_Y);
-    parallel_for(nlive, [&](int li) {
-        const int i = live[li];
-        const size_t bb = (size_t)b * b;
-        st[i] = finish_item(F, items[i], Yh + bb * li, frob + bb * i, col_pole + (size_t)b * i,
-                            col_prec + (size_t)b * i, lpoly + (size_t)4 * (b + 1) * i, errs[i]);
-        if (frob_scaled) std::memcpy(frob_scaled + bb * i, Yh + bb * li, 8 * bb);
-    });
-    const double finish_ms = ms_since(t2);
     cr_status first = CR_OK;
     for (int i = 0; i < count; i++) {
         if (item_status) item_status[i] = st[i];
@@ -819,26 +1013,77 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     }
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        for (int i : live) {
-            stats->start_blocks += items[i].nchain();
-            stats->column_steps += plans[i].column_steps;
-            stats->chunks += plans[i].chunks;
-            stats->vectors += plans[i].vectors;
-            stats->merged_terms += plans[i].merged_terms;
-            stats->combined_groups += plans[i].combined_groups;
+        stats->engine = -1;
+        stats->policy = fam->policy;
+        for (auto &sb : sub) {
+            for (int li = 0; li < (int)sb.live.size(); li++) {
+                const ItemPlan &pl = sb.plans[sb.live[li]];
+                stats->start_blocks += sb.items[sb.live[li]].nchain();
+                stats->column_steps += pl.column_steps;
+                stats->chunks += pl.chunks;
+                stats->vectors += pl.vectors;
+                stats->merged_terms += pl.merged_terms;
+                stats->combined_groups += pl.combined_groups;
+            }
+            stats->setup_ms += sb.setup_ms;
+            stats->device_ms += sb.dev_ms;
+            stats->reduce_ms += sb.red_ms - sb.comb_ms;
+            stats->combine_ms += sb.comb_ms;
+            stats->assemble_ms += sb.asm_ms;
+            stats->finish_ms += sb.finish_ms;
+            stats->phases = std::max(stats->phases, sb.nphase);
+            stats->fallbacks += sb.fallbacks;
+            if (!sb.live.empty()) {
+                const int e = sb.use_mfma ? (sb.use_bins ? 0 : 2) : 1;
+                // a sub-batch that fell back to the VALU kernel makes the call report it
+                if (stats->engine < 0 || e == 1) stats->engine = e;
+            }
         }
-        stats->setup_ms = setup_ms;
-        stats->device_ms = dev_ms;
-        stats->reduce_ms = red_ms - comb_ms;
-        stats->combine_ms = comb_ms;
-        stats->engine = use_mfma ? (use_bins ? 0 : 2) : 1;
-        stats->policy = policy;
-        stats->phases = nphase;
-        stats->fallbacks = fallbacks;
-        stats->assemble_ms = asm_ms;
-        stats->finish_ms = finish_ms;
+        if (stats->engine < 0) stats->engine = 0;
     }
     return first;
+}
+
+cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
+                      int32_t trials, cr_tuning *out, void *hip_stream) {
+    std::string err;
+    if (!check_family(fam, err) || !out || count <= 0 || trials < 1) return fail(CR_EINVAL, err.empty() ? "bad arguments" : err);
+    int32_t nco, s_dim, b;
+    cr_query_dims(fam->nvars, fam->degree, &nco, &s_dim, &b);
+    std::vector<uint64_t> frob((size_t)count * b * b);
+    std::vector<int32_t> pole((size_t)count * b), prec((size_t)count * b), ist(count);
+    std::vector<int64_t> lp((size_t)count * (b + 1) * 4);
+    std::memset(out, 0, sizeof(*out));
+    for (double &x : out->ms) x = -1;
+    out->best_ms = -1;
+    std::vector<int> pols = {CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR};
+    if (fam->mlp) pols.push_back(CR_POLICY_LEARNED);
+    for (int pol : pols)
+        for (int lm = 0; lm < 3; lm++) {
+            cr_family f = *fam;
+            f.policy = pol;
+            f.launch = lm;
+            if (!check_family(&f, err)) continue;
+            double tot = 0;
+            bool ok = true;
+            for (int r = 0; r <= trials && ok; r++) {
+                auto t0 = std::chrono::steady_clock::now();
+                cr_status st = cr_frobenius_batch(&f, count, primes, coeffs, frob.data(), nullptr, pole.data(),
+                                                  prec.data(), lp.data(), ist.data(), nullptr, hip_stream);
+                if (st != CR_OK) ok = false;
+                if (r > 0) tot += ms_since(t0);
+            }
+            if (!ok) continue;
+            const double ms = tot / trials;
+            out->ms[pol * 3 + lm] = ms;
+            if (out->best_ms < 0 || ms < out->best_ms) {
+                out->best_ms = ms;
+                out->best_policy = pol;
+                out->best_launch = lm;
+            }
+        }
+    if (out->best_ms < 0) return fail(CR_EINVAL, "no configuration ran: " + g_err);
+    return CR_OK;
 }
 
 }  // extern "C"

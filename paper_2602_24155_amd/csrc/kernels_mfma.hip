@@ -20,6 +20,8 @@
 // multiple of p^M, so the final values reduced mod p^M are the exact ones.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_layout.hpp"
 
 namespace crf {
@@ -385,26 +387,21 @@ __device__ __forceinline__ static void put_digits(int8_t *xp, double x, double Q
     }
 }
 
+// One tile (up to 32 vectors of one item) of the register-gather kernel.
+// colmapL / dirsL hold the family tables and sl this lane's bin slots.
 template <int NRT, int NKB, int D, int NV, bool Z32>
-__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const DevDigitItem *__restrict__ items,
-                                                           const DevTile *__restrict__ tiles,
-                                                           const int16_t *__restrict__ cu,
-                                                           const int32_t *__restrict__ cg,
-                                                           const int32_t *__restrict__ cpole,
-                                                           const DevVec *__restrict__ vx,
-                                                           uint64_t *__restrict__ store,
-                                                           uint64_t *__restrict__ hbuf,
-                                                           const uint32_t *__restrict__ slots, int *__restrict__ err) {
+__device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const DevTile &tile,
+                                                  const DevDigitItem *__restrict__ items,
+                                                  const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
+                                                  const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
+                                                  uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf,
+                                                  const uint32_t (&sl)[16], int *__restrict__ err, int8_t *Xbuf,
+                                                  const int16_t *colmapL, const int8_t *dirsL) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
     constexpr int NT = 64 * NRT;
     constexpr int XB = D * kCT * XS;  // bytes of one set of digit planes
-    __shared__ __align__(16) int8_t Xbuf[2 * XB];
-    __shared__ int16_t colmapL[kTabCap];
-    __shared__ int8_t dirsL[512];
     const int s = fam.s, nv = fam.nv, F = fam.F, n = fam.n;
-
-    const DevTile tile = tiles[blockIdx.x];
     const DevDigitItem it = items[tile.item];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 31, half = lane >> 5, bin = 2 * wave + half;
@@ -416,11 +413,6 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
 #pragma unroll
         for (int kb = 0; kb < NKB; kb++)
             A[i][kb] = *reinterpret_cast<const v4i *>(it.apack + ((((size_t)wave * D + i) * NKB + kb) * 64 + lane) * 16);
-    uint32_t sl[16];
-#pragma unroll
-    for (int j = 0; j < 16; j++) sl[j] = slots[bin * 16 + j];
-    for (int idx = tid; idx < fam.ndir * s; idx += NT) colmapL[idx] = fam.colmap[idx];
-    for (int idx = tid; idx < fam.ndir * nv; idx += NT) dirsL[idx] = fam.dirs[idx];
     for (int idx = tid; idx < 2 * XB / 16; idx += NT) reinterpret_cast<v4i *>(Xbuf)[idx] = v4i{0, 0, 0, 0};
     for (int idx = tid; idx < nch * F; idx += NT)
         if (vx[tile.chain0 + idx / F].out < 0) hbuf[(size_t)tile.chain0 * F + idx] = 0;
@@ -610,6 +602,78 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const 
     }
 }
 
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__device__ __forceinline__ static void mfma4_prologue(const DevFamily &fam, const uint32_t *__restrict__ slots,
+                                                      uint32_t (&sl)[16], int16_t *colmapL, int8_t *dirsL) {
+    constexpr int NT = 64 * NRT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, bin = 2 * wave + (lane >> 5);
+#pragma unroll
+    for (int j = 0; j < 16; j++) sl[j] = slots[bin * 16 + j];
+    for (int idx = tid; idx < fam.ndir * fam.s; idx += NT) colmapL[idx] = fam.colmap[idx];
+    for (int idx = tid; idx < fam.ndir * fam.nv; idx += NT) dirsL[idx] = fam.dirs[idx];
+    // the tile body's first barrier publishes the tables
+}
+
+// One workgroup per tile.
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4(DevFamily fam, const DevDigitItem *__restrict__ items,
+                                                           const DevTile *__restrict__ tiles,
+                                                           const int16_t *__restrict__ cu,
+                                                           const int32_t *__restrict__ cg,
+                                                           const int32_t *__restrict__ cpole,
+                                                           const DevVec *__restrict__ vx,
+                                                           uint64_t *__restrict__ store,
+                                                           uint64_t *__restrict__ hbuf,
+                                                           const uint32_t *__restrict__ slots, int *__restrict__ err) {
+    constexpr int XB = D * kCT * (NKB * 32 + 16);
+    __shared__ __align__(16) int8_t Xbuf[2 * XB];
+    __shared__ int16_t colmapL[kTabCap];
+    __shared__ int8_t dirsL[512];
+    uint32_t sl[16];
+    mfma4_prologue<NRT, NKB, D, NV, Z32>(fam, slots, sl, colmapL, dirsL);
+    mfma4_tile<NRT, NKB, D, NV, Z32>(fam, tiles[blockIdx.x], items, cu, cg, cpole, vx, store, hbuf, sl, err, Xbuf,
+                                     colmapL, dirsL);
+}
+
+// Persistent form: a grid sized to the resident capacity of the device drains
+// the tile list through an atomic counter (*queue, zero at launch).  Tiles
+// are ordered longest first, so the last tiles taken are the short ones.
+// Every workgroup leaves the loop once the counter passes ntiles.
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma4_persistent(
+    DevFamily fam, const DevDigitItem *__restrict__ items, const DevTile *__restrict__ tiles, int ntiles,
+    int *__restrict__ queue, const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
+    const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx, uint64_t *__restrict__ store,
+    uint64_t *__restrict__ hbuf, const uint32_t *__restrict__ slots, int *__restrict__ err) {
+    constexpr int XB = D * kCT * (NKB * 32 + 16);
+    __shared__ __align__(16) int8_t Xbuf[2 * XB];
+    __shared__ int16_t colmapL[kTabCap];
+    __shared__ int8_t dirsL[512];
+    __shared__ int next;
+    uint32_t sl[16];
+    mfma4_prologue<NRT, NKB, D, NV, Z32>(fam, slots, sl, colmapL, dirsL);
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int ti = next;
+        __syncthreads();  // every thread has read `next` before it is overwritten
+        if (ti >= ntiles) break;
+        mfma4_tile<NRT, NKB, D, NV, Z32>(fam, tiles[ti], items, cu, cg, cpole, vx, store, hbuf, sl, err, Xbuf,
+                                         colmapL, dirsL);
+    }
+}
+
+__global__ void k_zero_ints(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
 bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
     nrt = (fam.nsrc + 31) / 32;
     nkb = (fam.T + 31) / 32;
@@ -620,7 +684,24 @@ bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
 template <int R, int KB, int DD, bool ZZ>
 static hipError_t launch_one4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
-                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, hipStream_t stream) {
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
+                              hipStream_t stream) {
+    if (pgrid > 0) {
+        // resident workgroups per CU of this instance, times the CU count, times pgrid
+        static int per_device = 0;
+        if (per_device == 0) {
+            int dev = 0, cus = 0, per_cu = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reduce_mfma4_persistent<R, KB, DD, 3, ZZ>,
+                                                               64 * R, 0);
+            per_device = std::max(1, cus) * std::max(1, per_cu);
+        }
+        const int grid = std::min(ntiles, per_device * pgrid);
+        hipLaunchKernelGGL((k_reduce_mfma4_persistent<R, KB, DD, 3, ZZ>), dim3(grid), dim3(64 * R), 0, stream, fam,
+                           items, tiles, ntiles, queue, cu, cg, cpole, vx, store, hbuf, slots, err);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_reduce_mfma4<R, KB, DD, 3, ZZ>), dim3(ntiles), dim3(64 * R), 0, stream, fam, items, tiles, cu,
                        cg, cpole, vx, store, hbuf, slots, err);
     return hipGetLastError();
@@ -635,7 +716,7 @@ bool mfma4_supports(const DevFamily &fam, int D) {
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                                const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
                                uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
-                               hipStream_t stream) {
+                               int pgrid, int *queue, hipStream_t stream) {
     if (ntiles == 0) return hipSuccess;
     int nrt, nkb;
     if (!mfma4_supports(fam, D)) return hipErrorInvalidValue;
@@ -644,9 +725,9 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
     if (nrt == R && nkb == KB && D == DD) {                                                                             \
         if (z32)                                                                                                        \
             return launch_one4<R, KB, DD, true>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,  \
-                                                stream);                                                                \
+                                                pgrid, queue, stream);                                                  \
         return launch_one4<R, KB, DD, false>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,     \
-                                             stream);                                                                   \
+                                             pgrid, queue, stream);                                                     \
     }
     CRF_LAUNCH4(2, 2, 3)
     CRF_LAUNCH4(2, 2, 6)

@@ -85,3 +85,15 @@ def test_bad_prime_statuses_without_device():
         C.cr_check_smooth(fam, 9, [1] * 21)
     with pytest.raises(C.CrError):
         C.cr_check_smooth(fam, 53, [1] * 21)
+
+
+def test_family_options_are_validated():
+    items = [(31, [1] * 21)]
+    for kw in ({"launch": 3}, {"policy": 7}, {"engine": 5},
+               {"engine": C.ENGINE_MFMA_LDS, "policy": C.CR_POLICY_P_CHUNK}):
+        with pytest.raises(C.CrError) as e:
+            C.cr_frobenius_batch(C.family(3, 5, **kw), [p for p, _ in items], [c for _, c in items])
+        assert e.value.status == C.CR_EINVAL, kw
+    with pytest.raises(C.CrError) as e:
+        C.cr_autotune(C.family(3, 5), [31], [[1] * 21], trials=0)
+    assert e.value.status == C.CR_EINVAL
