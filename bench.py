@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
-KERNEL_NAMES = {0: "k_reduce_mfma4", 1: "k_reduce_chains", 2: "k_reduce_mfma"}
+KERNEL_NAMES = {0: "k_reduce_mfma4", 1: "k_reduce_chains", 2: "k_reduce_mfma"}  # engine -> kernel (grid launch)
 
 
 def measured_traffic(workload):
@@ -182,7 +182,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / INT8_PEAK_TOPS,
                      "traffic": measured_traffic(args.workload) if st.engine == 0 else None,
-                     "kernel": KERNEL_NAMES.get(st.engine, "?"),
+                     "kernel": KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 0 and fam.launch > 0
+                                                                    else ""),
                      "work_per_column_step_int8_ops": work_per_colstep},
     }
     if not args.no_cpu_baseline:

@@ -28,6 +28,7 @@ hipError_t launch_combine(const DevItem *items, const DevComb *comb, int ncomb, 
 hipError_t launch_assemble(const DevFamily &fam, const DevItem *items, int nitems, const uint64_t *hbuf,
                            hipStream_t stream);
 bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb);
+bool mfma4_shape(const DevFamily &fam, int &nrt, int &nkb);
 hipError_t launch_reduce_mfma(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, uint64_t *hbuf, int *err,
                               int D, hipStream_t stream);
@@ -137,8 +138,14 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
     e->off_dirs = put(F.dirs.exps.data(), F.dirs.exps.size());
     e->off_finU = put(F.finU.exps.data(), std::max<size_t>(F.finU.exps.size(), 1));
     {
-        const int nrt = (F.nsrc + 31) / 32;
-        e->bl_ok = nrt >= 1 && nrt <= 3 && bin_layout(F, nrt, e->bl);
+        DevFamily shape{};
+        shape.nsrc = F.nsrc;
+        shape.T = F.tgt.count;
+        shape.s = F.g.count;
+        shape.ndir = F.dirs.count;
+        shape.nv = F.nv;
+        int nrt = 0, nkb = 0;
+        e->bl_ok = mfma4_shape(shape, nrt, nkb) && bin_layout(F, nrt, e->bl);
         if (!e->bl_ok) e->bl.slot.assign(16, 0);
         e->off_slots = put(e->bl.slot.data(), e->bl.slot.size() * 4);
     }
@@ -332,9 +339,10 @@ struct BatchCtx {
         df.ndir = F->dirs.count;
         df.nfinU = F->finU.count;
         policy = f->policy;
-        want_mfma = (f->engine == 0 || f->engine == 2) && mfma_shape(df, nrt, nkb);
         // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
         use_bins = f->engine == 0 && fe->bl_ok;
+        want_mfma = (f->engine == 0 || f->engine == 2) &&
+                    (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
         return true;
     }
 };

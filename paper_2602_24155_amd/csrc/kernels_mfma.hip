@@ -707,10 +707,20 @@ static hipError_t launch_one4(const DevFamily &fam, const DevDigitItem *items, c
     return hipGetLastError();
 }
 
+// Shape of the register-gather kernel: up to 64 source rows in 2 row tiles
+// (2 waves), up to 128 in 4 (4 waves: every SIMD of the CU gets one wave and
+// the outputs spread over 8 lane bins).
+bool mfma4_shape(const DevFamily &fam, int &nrt, int &nkb) {
+    nrt = fam.nsrc <= 64 ? 2 : (fam.nsrc <= 128 ? 4 : 0);
+    nkb = (fam.T + 31) / 32;
+    return nrt > 0 && ((nrt == 2 && nkb == 2) || (nrt == 4 && nkb == 3)) && fam.ndir * fam.s <= kTabCap &&
+           fam.nv <= 8;
+}
+
 bool mfma4_supports(const DevFamily &fam, int D) {
     int nrt, nkb;
-    if (!mfma_shape(fam, nrt, nkb) || fam.nv != 3 || fam.ndir * fam.nv > 512) return false;
-    return (nrt == 2 && (D == 3 || D == 6)) || (nrt == 3 && (D == 5 || D == 8 || D == 10));
+    if (!mfma4_shape(fam, nrt, nkb) || fam.nv != 3 || fam.ndir * fam.nv > 512) return false;
+    return (nrt == 2 && (D == 3 || D == 6)) || (nrt == 4 && (D == 5 || D == 8 || D == 10));
 }
 
 hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
@@ -720,7 +730,7 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
     if (ntiles == 0) return hipSuccess;
     int nrt, nkb;
     if (!mfma4_supports(fam, D)) return hipErrorInvalidValue;
-    mfma_shape(fam, nrt, nkb);
+    mfma4_shape(fam, nrt, nkb);
 #define CRF_LAUNCH4(R, KB, DD)                                                                                          \
     if (nrt == R && nkb == KB && D == DD) {                                                                             \
         if (z32)                                                                                                        \
@@ -731,9 +741,9 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
     }
     CRF_LAUNCH4(2, 2, 3)
     CRF_LAUNCH4(2, 2, 6)
-    CRF_LAUNCH4(3, 3, 5)
-    CRF_LAUNCH4(3, 3, 8)
-    CRF_LAUNCH4(3, 3, 10)
+    CRF_LAUNCH4(4, 3, 5)
+    CRF_LAUNCH4(4, 3, 8)
+    CRF_LAUNCH4(4, 3, 10)
 #undef CRF_LAUNCH4
     return hipErrorInvalidValue;
 }
