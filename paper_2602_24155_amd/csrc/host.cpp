@@ -781,13 +781,10 @@ bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams 
         }
         return Zmax * acc;
     };
-    int h = -1;
-    for (int cand = 1; cand <= D; cand++)
-        if (span(cand, D) < lim && span(0, cand) < lim) {
-            h = cand;
-            break;
-        }
-    if (h < 0) return false;
+    // Horner split at h = D/2 (a constant of the kernel instance): both halves
+    // must stay exact in fp64
+    const int h = D / 2;
+    if (!(span(h, D) < lim && span(0, h) < lim)) return false;
     // digit split: x in [0, Q') as x_hi B^ds + x_lo with both parts below 2^24
     const int ds = (D + 1) / 2;
     long double Bds = 1, Brest = 1;

@@ -318,22 +318,23 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma(DevFamily fam, const D
 // slots[bin*16 + j] (bin = 2*wave + lane/32) packs: bit0 valid, bit1 ends the
 // output's group, bits 2-4 the variable i of the source row, bits 5-15 the
 // constant weight r_i + [i not in S], bits 16-31 the output r.
+template <int NV>
 __device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, const int8_t *dirsL, const int *U,
                                                         int poles_left, int *v, int &dir, int &k) {
     int left = fam.d;
 #pragma unroll
-    for (int i = 0; i < 8; i++) v[i] = 0;
+    for (int i = 0; i < NV; i++) v[i] = 0;
 #pragma unroll
-    for (int sI = 0; sI < 8; sI++)
-        if (sI < fam.nv && left > 0 && ((fam.smask >> sI) & 1u) && U[sI] != 0) {
+    for (int sI = 0; sI < NV; sI++)
+        if (left > 0 && ((fam.smask >> sI) & 1u) && U[sI] != 0) {
             v[sI] = 1;
             left--;
         }
     for (int guard = 0; guard < 64 && left > 0; guard++) {
         bool moved = false;
 #pragma unroll
-        for (int m = 0; m < 8; m++)
-            if (m < fam.nv && left > 0 && v[m] < U[m]) {
+        for (int m = 0; m < NV; m++)
+            if (left > 0 && v[m] < U[m]) {
                 v[m]++;
                 left--;
                 moved = true;
@@ -342,14 +343,13 @@ __device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, co
     }
     k = poles_left;
 #pragma unroll
-    for (int i = 0; i < 8; i++)
-        if (i < fam.nv && v[i]) k = min(k, U[i] / v[i]);
+    for (int i = 0; i < NV; i++)
+        if (v[i]) k = min(k, U[i] / v[i]);
     dir = -1;
     for (int t = 0; t < fam.ndir && dir < 0; t++) {
         bool eq = true;
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (i < fam.nv) eq = eq && (dirsL[t * fam.nv + i] == v[i]);
+        for (int i = 0; i < NV; i++) eq = eq && (dirsL[t * NV + i] == v[i]);
         if (eq) dir = t;
     }
 }
@@ -389,6 +389,8 @@ __device__ __forceinline__ static void put_digits(int8_t *xp, double x, double Q
 
 // One tile (up to 32 vectors of one item) of the register-gather kernel.
 // colmapL / dirsL hold the family tables and sl this lane's bin slots.
+// One tile (up to 32 vectors of one item) of the register-gather kernel.
+// colmapL / dirsL hold the family tables and sl this lane's bin slots.
 template <int NRT, int NKB, int D, int NV, bool Z32>
 __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const DevTile &tile,
                                                   const DevDigitItem *__restrict__ items,
@@ -401,7 +403,7 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
     constexpr int XS = K + 16;
     constexpr int NT = 64 * NRT;
     constexpr int XB = D * kCT * XS;  // bytes of one set of digit planes
-    const int s = fam.s, nv = fam.nv, F = fam.F, n = fam.n;
+    const int s = fam.s, F = fam.F, n = fam.n;
     const DevDigitItem it = items[tile.item];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 31, half = lane >> 5, bin = 2 * wave + half;
@@ -424,19 +426,19 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
 
     const double Bd = it.Bd, Qd = it.Qd, invQ = it.invQ, BHd = it.BHd, invBH = it.invBH, Bh = it.Bh;
     const double Bsplit = it.Bsplit, invBsplit = it.invBsplit, bias = it.bias;
-    const int h = it.h, Bi = it.B, halfB = it.halfB, shift = it.shift;
+    const int Bi = it.B, halfB = it.halfB, shift = it.shift;
     const uint32_t magic = it.magic;
+    const double qd = (double)it.q, invq = 1.0 / qd;  // p^M < Q' < 2^52: mod_fp is exact
 
     // chain state (registers; identical in every lane of chain c)
-    int U[8], V[8], dir = 0, kleft = 0, pole = n, pend = n, vout = -1;
+    int U[NV], V[NV], dir = 0, kleft = 0, pole = n, pend = n, vout = -1;
 #pragma unroll
-    for (int i = 0; i < 8; i++) U[i] = V[i] = 0;
+    for (int i = 0; i < NV; i++) U[i] = V[i] = 0;
     if (c < nch) {
         const int g = tile.chain0 + c;
         const DevVec xv = vx[g];
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (i < nv) U[i] = cu[(size_t)g * nv + i];
+        for (int i = 0; i < NV; i++) U[i] = cu[(size_t)g * NV + i];
         pole = cpole[g];
         pend = xv.pend;
         vout = xv.out;
@@ -445,10 +447,9 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
             d0 = xv.dir;
             k0 = pole - pend;
 #pragma unroll
-            for (int i = 0; i < 8; i++)
-                if (i < nv) V[i] = dirsL[d0 * nv + i];
+            for (int i = 0; i < NV; i++) V[i] = dirsL[d0 * NV + i];
         } else {
-            choose_chunk_reg(fam, dirsL, U, pole - pend, V, d0, k0);
+            choose_chunk_reg<NV>(fam, dirsL, U, pole - pend, V, d0, k0);
         }
         if (d0 < 0 || k0 < 1) {
             if (wave == 0 && half == 0) atomicOr(err, 1);
@@ -501,16 +502,16 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
         }
         // bookkeeping of this lane's chain: exponent after the step, next direction
         const bool act = pole > pend;
-        int up[8], Vn[8], dirn = dir, kleftn = kleft - 1;
+        int up[NV], Vn[NV], dirn = dir, kleftn = kleft - 1;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
+        for (int i = 0; i < NV; i++) {
             up[i] = U[i] - (act ? V[i] : 0);
             Vn[i] = V[i];
         }
         const bool more = act && pole - 1 > pend;
         if (more && kleftn == 0) {
             int d0, k0;
-            choose_chunk_reg(fam, dirsL, up, pole - 1 - pend, Vn, d0, k0);
+            choose_chunk_reg<NV>(fam, dirsL, up, pole - 1 - pend, Vn, d0, k0);
             if (d0 < 0 || k0 < 1) {
                 atomicOr(err, 1);
                 d0 = 0;
@@ -518,6 +519,19 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
             }
             dirn = d0;
             kleftn = k0;
+        }
+        // a chain that ends here at pole n: row of its final exponent in finmap
+        int fin_row = -1;
+        if (act && !more && vout < 0) {
+            int Ui = -1;
+            for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
+                bool eq = true;
+#pragma unroll
+                for (int i = 0; i < NV; i++) eq = eq && (fam.finU[a * NV + i] == up[i]);
+                if (eq) Ui = a;
+            }
+            if (Ui < 0) atomicOr(err, 4);
+            else fin_row = Ui * s;
         }
         __syncthreads();  // every wave has read the current digit planes
         if (act) {
@@ -549,11 +563,12 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
                 // output r complete: w'[r] = sum_k Z_k B^k mod Q'
                 const int r = (int)(w >> 16);
                 if (r == 0xFFFF) continue;  // unused group slot
+                constexpr int H = D / 2;  // Horner split (host checks both halves stay exact)
                 double lo = 0.0, hi = 0.0;
 #pragma unroll
                 for (int k = D - 1; k >= 0; k--) {
                     const double zk = Z32 ? (double)zi[k] : zd[k];
-                    if (k >= h) hi = fma(hi, Bd, zk);
+                    if (k >= H) hi = fma(hi, Bd, zk);
                     else lo = fma(lo, Bd, zk);
                     zi[k] = 0;
                     zd[k] = 0.0;
@@ -570,17 +585,11 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
                     }
                     put_digits<D, XS>(Xn + c * XS + col, x, Qd, bias, Bsplit, invBsplit, magic, shift, Bi, halfB);
                 } else if (vout >= 0) {
-                    store[(size_t)vout * s + r] = (uint64_t)x % it.q;  // combine point
-                } else {
-                    int Ui = -1;
-                    for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
-                        bool eq = true;
-                        for (int i = 0; i < nv; i++) eq = eq && (fam.finU[a * nv + i] == up[i]);
-                        if (eq) Ui = a;
-                    }
-                    const int f = Ui < 0 ? -1 : fam.finmap[Ui * s + r];
+                    store[(size_t)vout * s + r] = (uint64_t)mod_fp(x, qd, invq);  // combine point
+                } else if (fin_row >= 0) {
+                    const int f = fam.finmap[fin_row + r];
                     if (f < 0) atomicOr(err, 4);
-                    else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)x % it.q;
+                    else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)mod_fp(x, qd, invq);
                 }
             }
         }
@@ -588,7 +597,7 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
         int8_t *Xz = Xbuf + cur * XB;
         for (int idx = tid; idx < XB / 16; idx += NT) reinterpret_cast<v4i *>(Xz)[idx] = v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
+        for (int i = 0; i < NV; i++) {
             U[i] = up[i];
             V[i] = Vn[i];
         }
