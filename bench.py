@@ -134,12 +134,12 @@ def main():
         fam.launch = launch_names.index(args.launch)
 
     for _ in range(args.warmup):
-        C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
+        C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
     torch.cuda.synchronize()
     tot = {"reduce_ms": 0.0, "combine_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False)
+        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
         for k in tot:
             tot[k] += getattr(res["stats"], k)
     torch.cuda.synchronize()

@@ -154,8 +154,10 @@ def _lpoly_ints(words):
     return out
 
 
-def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise_on_error=True):
-    """Run the whole path for a batch; returns a dict of numpy arrays / lists."""
+def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise_on_error=True, lpoly_ints=True):
+    """Run the whole path for a batch; returns a dict of numpy arrays / lists.
+    With lpoly_ints=False, "lpoly" is the raw (count, b+1, 4) array of 256-bit
+    two's-complement words instead of lists of Python integers."""
     primes = np.ascontiguousarray(np.asarray(primes, dtype=np.int32))
     count = int(primes.shape[0])
     nco, _s, b = cr_query_dims(fam.nvars, fam.degree)
@@ -177,7 +179,7 @@ def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise
         _check(st)
     return {
         "status": st, "item_status": ist, "frob": frob, "scaled": scaled, "col_pole": pole,
-        "col_prec": prec, "lpoly": [_lpoly_ints(lp[i]) for i in range(count)], "stats": stats,
+        "col_prec": prec, "lpoly": [_lpoly_ints(lp[i]) for i in range(count)] if lpoly_ints else lp, "stats": stats,
     }
 
 

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -154,21 +156,83 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
     return raw;
 }
 
+// Persistent worker threads for the per-item host work (at most 16 threads in
+// all, the caller included).  A call from inside a task runs serially.
+class Pool {
+  public:
+    static Pool &get() {
+        static Pool p;
+        return p;
+    }
+    void run(int count, const std::function<void(int)> &fn) {
+        if (count <= 0) return;
+        if (in_task || workers_.empty() || count == 1) {
+            for (int i = 0; i < count; i++) fn(i);
+            return;
+        }
+        std::unique_lock<std::mutex> lk(m_);
+        job_ = &fn;
+        count_ = count;
+        next_ = 0;
+        busy_ = (int)workers_.size();
+        gen_++;
+        cv_.notify_all();
+        lk.unlock();
+        drain();
+        lk.lock();
+        done_.wait(lk, [&] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+            gen_++;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+
+  private:
+    Pool() {
+        int hw = (int)std::thread::hardware_concurrency();
+        const int n = std::max(0, std::min(hw > 0 ? hw : 1, 16) - 1);
+        for (int t = 0; t < n; t++) workers_.emplace_back([this] { loop(); });
+    }
+    void drain() {
+        in_task = true;
+        for (int i = next_++; i < count_; i = next_++) (*job_)(i);
+        in_task = false;
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            std::unique_lock<std::mutex> lk(m_);
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (stop_) return;
+            lk.unlock();
+            drain();
+            lk.lock();
+            if (--busy_ == 0) done_.notify_all();
+        }
+    }
+    static thread_local bool in_task;
+    std::vector<std::thread> workers_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    std::atomic<int> next_{0};
+    int count_ = 0, busy_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+thread_local bool Pool::in_task = false;
+
 template <class Fn>
 void parallel_for(int count, Fn fn) {
-    int hw = (int)std::thread::hardware_concurrency();
-    int nt = std::max(1, std::min({count, hw > 0 ? hw : 1, 16}));
-    if (nt == 1) {
-        for (int i = 0; i < count; i++) fn(i);
-        return;
-    }
-    std::atomic<int> next{0};
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; t++)
-        th.emplace_back([&]() {
-            for (int i = next++; i < count; i = next++) fn(i);
-        });
-    for (auto &x : th) x.join();
+    const std::function<void(int)> f = fn;
+    Pool::get().run(count, f);
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -327,6 +391,10 @@ struct BatchCtx {
         cr_query_dims(f->nvars, f->degree, &nco_, &s_dim, &b_);
         nco = nco_;
         b = b_;
+        if (b > 256) {
+            err = "basis larger than 256 columns";
+            return false;
+        }
         sdim = F->g.count;
         df.nv = F->nv;
         df.n = F->n;
@@ -985,7 +1053,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     if (!ctx.init(fam, primes, coeffs, reinterpret_cast<hipStream_t>(hip_stream), err)) return fail(CR_EINVAL, err);
     ctx.out = {frob, frob_scaled, col_pole, col_prec, lpoly};
     // Sub-batches: the host prepares sub-batch k + 1 while the device reduces sub-batch k.
-    const int S = count >= 128 ? 4 : (count >= 48 ? 2 : 1);
+    const int S = count >= 192 ? 8 : (count >= 96 ? 4 : (count >= 48 ? 2 : 1));
     std::vector<SubBatch> sub(S);
     for (int k = 0; k < S; k++) {
         const int a = (int)((int64_t)count * k / S), z = (int)((int64_t)count * (k + 1) / S);

@@ -336,6 +336,20 @@ static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int 
     std::vector<int> piv(R, -1), nz;
     std::vector<char> used(C, 0);
     nz.reserve(W);
+    // Shoup's quotient floor(y 2^64 / q) of a multiplier y < q from the 128-bit
+    // reciprocal floor((2^128 - 1) / q): the estimate (y * rq) >> 64 is at most 2
+    // below the true value, fixed by comparing y 2^64 - est q with q
+    u128 rq = ~(u128)0 / q;
+    auto shoup = [&](u64 y) {
+        const u128 yh = (u128)y * (u64)(rq >> 64), yl = (u128)y * (u64)rq;
+        u64 est = (u64)((yh + (yl >> 64)));
+        u128 rem = ((u128)y << 64) - (u128)est * q;
+        while (rem >= q) {
+            rem -= q;
+            est++;
+        }
+        return est;
+    };
     for (int r = 0; r < R; r++) {
         u64 *row = &a[(size_t)r * W];
         int c = -1;
@@ -359,7 +373,7 @@ static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int 
             if (!f) continue;
             // o -= f * row (mod q) with Shoup's precomputed quotient of f
             const u64 nf = q - f;
-            const u64 fs = (u64)(((u128)nf << 64) / q);
+            const u64 fs = shoup(nf);
             for (int k : nz) {
                 const u64 x = row[k];
                 const u64 qh = (u64)(((u128)fs * x) >> 64);
@@ -736,7 +750,6 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
             out.chain_pole[k] = poles[order[k]];
             std::memcpy(&coef2[k * b], &coef[(size_t)order[k] * b], sizeof(u64) * b);
             out.column_steps += poles[order[k]] - n;
-            count_chunks(fam, &out.chain_u[k * nv], poles[order[k]], out.chunks);
         }
         coef.swap(coef2);
     }
@@ -910,12 +923,16 @@ void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &
     const long long B = dp.B;
     const u64 Q = dp.Qp, bias = (Q - 1) / 2;
     std::vector<int8_t> dig((size_t)fam.nsrc * T * D);
+    // x / B as the high product with ceil(2^64 / B): it never undershoots and
+    // overshoots by at most one for x < 2^52, which the remainder test corrects
+    const u64 rB = ~0ull / (u64)B + 1;
     for (size_t e = 0; e < (size_t)fam.nsrc * T; e++) {
         // balanced digits of x = unsigned digits of (x + (Q-1)/2) mod Q, minus (B-1)/2
         u64 x = it.psi[e] + bias;
         if (x >= Q) x -= Q;
         for (int i = 0; i < D; i++) {
-            const u64 qd = x / (u64)B;
+            u64 qd = (u64)(((u128)x * rB) >> 64);
+            if (qd * (u64)B > x) qd--;
             dig[e * D + i] = (int8_t)((int)(x - qd * (u64)B) - half);
             x = qd;
         }

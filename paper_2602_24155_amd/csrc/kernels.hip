@@ -18,8 +18,8 @@
 // its whole range (the learned policy).
 //
 // k_combine: store rows built between phases (like terms combined, Section 3.4).
-// k_assemble: H = sum coef (x) h over the vectors that reach pole n, and
-// Y = rho H (Section 3.3 step (2)).
+// k_assemble_h / k_assemble_y: H = sum coef (x) h over the vectors that reach
+// pole n, and Y = rho H (Section 3.3 step (2)).
 #include <hip/hip_runtime.h>
 
 #include "device_layout.hpp"
@@ -234,23 +234,46 @@ __global__ __launch_bounds__(64) void k_combine(const DevItem *__restrict__ item
     }
 }
 
-// One workgroup per item: H = sum_k h_k (x) coef_k over the vectors that reach
-// pole n, then Y = rho H.
-__global__ __launch_bounds__(kThreads) void k_assemble(DevFamily fam, const DevItem *__restrict__ items,
-                                                       const u64 *__restrict__ hbuf) {
+// H = sum_k h_k (x) coef_k over the vectors that reach pole n: one workgroup
+// per (item, row f of H).  Thread t takes column c = t mod b and every
+// (kThreads / b)-th vector of its slice; the slices are summed in LDS.
+__global__ __launch_bounds__(kThreads) void k_assemble_h(DevFamily fam, const DevItem *__restrict__ items,
+                                                         const u64 *__restrict__ hbuf) {
+    __shared__ u64 part[kThreads];
+    const DevItem it = items[blockIdx.x];
+    const int f = blockIdx.y;
+    const DMod md{it.q, it.mu, it.sbits};
+    const int F = fam.F, b = it.b, t = threadIdx.x;
+    const int nsl = kThreads / b;  // b <= kThreads
+    const int c = t % b, sl = t / b;
+    u64 r = 0;
+    if (sl < nsl) {
+        u128 acc = 0;
+        int cnt = 0;
+        for (int k = sl; k < it.nfin; k += nsl) {
+            const u64 h = hbuf[(size_t)it.fvec[k] * F + f];
+            if (h) acc += (u128)h * it.coef[(size_t)it.frow[k] * b + c];
+            if (++cnt == 128) {
+                acc = md.reduce(acc);
+                cnt = 0;
+            }
+        }
+        r = md.reduce(acc);
+    }
+    part[t] = r;
+    __syncthreads();
+    if (t < b) {
+        u128 acc = 0;
+        for (int j = 0; j < nsl; j++) acc += part[j * b + t];
+        it.H[(size_t)f * b + t] = md.reduce(acc);
+    }
+}
+
+// Y = rho H, one workgroup per item.
+__global__ __launch_bounds__(kThreads) void k_assemble_y(DevFamily fam, const DevItem *__restrict__ items) {
     const DevItem it = items[blockIdx.x];
     const DMod md{it.q, it.mu, it.sbits};
     const int F = fam.F, b = it.b;
-    for (int idx = threadIdx.x; idx < F * b; idx += kThreads) {
-        const int f = idx / b, c = idx - f * b;
-        u128 acc = 0;
-        for (int k = 0; k < it.nfin; k++) {
-            acc += (u128)hbuf[(size_t)it.fvec[k] * F + f] * it.coef[(size_t)it.frow[k] * b + c];
-            if ((k & 127) == 127) acc = md.reduce(acc);
-        }
-        it.H[idx] = md.reduce(acc);
-    }
-    __syncthreads();
     for (int idx = threadIdx.x; idx < b * b; idx += kThreads) {
         const int i = idx / b, c = idx - i * b;
         u128 acc = 0;
@@ -286,7 +309,9 @@ hipError_t launch_combine(const DevItem *items, const DevComb *comb, int ncomb, 
 hipError_t launch_assemble(const DevFamily &fam, const DevItem *items, int nitems, const u64 *hbuf,
                            hipStream_t stream) {
     if (nitems == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_assemble, dim3(nitems), dim3(kThreads), 0, stream, fam, items, hbuf);
+    if (fam.F > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_assemble_h, dim3(nitems, fam.F), dim3(kThreads), 0, stream, fam, items, hbuf);
+    hipLaunchKernelGGL(k_assemble_y, dim3(nitems), dim3(kThreads), 0, stream, fam, items);
     return hipGetLastError();
 }
 
