@@ -24,11 +24,11 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
 KERNEL_NAMES = {0: "k_reduce_mfma4", 1: "k_reduce_chains", 2: "k_reduce_mfma"}  # engine -> kernel (grid launch)
 
 
-def measured_traffic(workload):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of the reduction kernel from the committed rocprofv3
     counters, if they were taken on the kernel source as it is now."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_reduce_mfma4_%s.json" % workload)
+    path = os.path.join(ROOT, "profiles", "%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     prof = json.load(open(path))
@@ -159,6 +159,7 @@ def main():
     work_per_colstep = work / len(primes)
     red_s = tot["reduce_ms"] / 1e3 / args.steps
     achieved = st.column_steps * work_per_colstep / red_s / 1e12
+    kname = KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 0 and fam.launch > 0 else "")
     line = {
         "metric": "Frobenius matrices/sec (batched quintic curves, p=31) + modular matvecs/sec vs plain",
         "value": value,
@@ -181,9 +182,9 @@ def main():
         "breakdown_ms": {k: v / args.steps for k, v in tot.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / INT8_PEAK_TOPS,
-                     "traffic": measured_traffic(args.workload) if st.engine == 0 else None,
-                     "kernel": KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 0 and fam.launch > 0
-                                                                    else ""),
+                     "traffic": measured_traffic(kname, args.workload),
+                     "kernel": kname, "launches_per_step": st.reduce_launches,
+                     "avg_launch_ms": tot["reduce_ms"] / args.steps / max(1, st.reduce_launches),
                      "work_per_column_step_int8_ops": work_per_colstep},
     }
     if not args.no_cpu_baseline:

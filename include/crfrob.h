@@ -124,6 +124,7 @@ typedef struct {
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
     int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a
                                 plain policy's and were reduced with the cheaper plain plan */
+    int64_t reduce_launches; /* launches of the reduction kernels (sub-batches x phases x digit groups) */
 } cr_stats;
 
 /* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},

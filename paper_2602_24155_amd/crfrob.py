@@ -50,7 +50,8 @@ class cr_stats(ctypes.Structure):
                 ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double),
                 ("assemble_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("engine", ctypes.c_int32), ("policy", ctypes.c_int32),
-                ("phases", ctypes.c_int32), ("fallbacks", ctypes.c_int32)]
+                ("phases", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("reduce_launches", ctypes.c_int64)]
 
 
 class CrError(RuntimeError):

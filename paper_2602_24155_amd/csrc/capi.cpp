@@ -1108,6 +1108,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             stats->assemble_ms += sb.asm_ms;
             stats->finish_ms += sb.finish_ms;
             stats->phases = std::max(stats->phases, sb.nphase);
+            stats->reduce_launches += (int64_t)sb.launches.size();
             stats->fallbacks += sb.fallbacks;
             if (!sb.live.empty()) {
                 const int e = sb.use_mfma ? (sb.use_bins ? 0 : 2) : 1;
