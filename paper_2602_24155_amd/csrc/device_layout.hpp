@@ -80,7 +80,7 @@ struct DevDigitItem {
     double bias;          // sum_j halfB B^j when digits are balanced, else 0
     uint64_t Qp;          // Q'
     uint64_t q;           // p^M (final reduction)
-    uint32_t magic;       // floor division by B of a value < 2^24: (v * magic) >> (32 + shift)
+    uint32_t magic;       // floor division by B of a value < 2^24: mulhi(v, magic) >> shift
     int32_t shift;
     int32_t B;
     int32_t halfB;        // subtracted from every digit when balanced, else 0
@@ -91,5 +91,19 @@ struct DevDigitItem {
     int32_t chain0, nchain;
     const int8_t *apack;  // NRT x D x NKB x 64 lanes x 16 bytes: psi digits in MFMA A-fragment order
 };
+
+}  // namespace crf
+
+namespace crf {
+
+// Lane-slot pattern of the register-gather kernel: the sizes of the output
+// groups held by one lane bin, the same in every bin (a group is the set of
+// source rows src(r, i) that feed output r; its rows sit at the end of its
+// slot, so the group ends on a fixed accumulator slot).  Quartic curves
+// (2 row tiles, 4 bins) and quintic curves (4 row tiles, 8 bins).
+constexpr int kSlotGroups2[] = {3, 3, 3, 1, 1, 1, 1};
+constexpr int kSlotGroups4[] = {3, 3, 3, 1, 1, 1};
+constexpr int slot_groups(int nrt) { return nrt == 2 ? 7 : (nrt == 4 ? 6 : 0); }
+constexpr int slot_group(int nrt, int g) { return nrt == 2 ? kSlotGroups2[g] : kSlotGroups4[g]; }
 
 }  // namespace crf

@@ -1,5 +1,6 @@
 // Host setup / finishing for controlled reduction (see host.hpp).
 #include "host.hpp"
+#include "device_layout.hpp"
 
 #include <algorithm>
 #include <array>
@@ -804,8 +805,12 @@ bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams 
     for (int k = 0; k < ds; k++) Bds *= B;
     for (int k = ds; k < D; k++) Brest *= B;
     if (Bds >= std::ldexp(1.0L, 24) || Brest >= std::ldexp(1.0L, 24)) return false;
+    // floor division by B of v < 2^24: (mulhi(v, magic) >> shift) with
+    // shift = floor(log2 B), magic = floor(2^(32 + shift) / B) + 1 < 2^32; exact
+    // when B^2 < 2^(8 + shift) (error v (magic B - 2^(32+shift)) / 2^(32+shift) < 1/B)
     int ell = 0;
-    while ((1LL << ell) < B) ell++;
+    while ((2LL << ell) <= B) ell++;
+    if ((long long)B * B >= (1LL << (8 + ell))) return false;
     dp.e = e;
     dp.B = (int)B;
     dp.D = D;
@@ -813,8 +818,8 @@ bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams 
     dp.ds = ds;
     dp.halfB = (int)half;
     dp.z32 = Zmax < std::ldexp(1.0L, 31) ? 1 : 0;
-    dp.shift = 24 + ell;
-    dp.magic = (uint32_t)(((1ULL << (24 + ell)) / (unsigned long long)B) + 1);
+    dp.shift = ell;
+    dp.magic = (uint32_t)(((1ULL << (32 + ell)) / (unsigned long long)B) + 1);
     dp.Qp = (u64)Q;
     dp.Bd = (double)B;
     dp.Qd = (double)dp.Qp;
@@ -854,32 +859,28 @@ bool bin_layout(const Family &fam, int nrt, BinLayout &bl) {
     }
     if (maxsz > 4) return false;
     bl.nbins = 2 * nrt;
-    // Every bin gets the same pattern of group slots (sizes 4, 3, 2, 1, largest
-    // first), so the group ends fall on the same accumulator slots in every
-    // lane and the per-output work never diverges.  Choose slot counts c_k with
-    // sum k c_k <= 16 such that groups of size >= k fit in slots of size >= k.
-    std::vector<int> G(5, 0);
-    for (auto &g : groups) G[g.members.size()]++;
-    int best[5] = {0, 0, 0, 0, 0}, bestslots = 1 << 30;
-    for (int c4 = 0; c4 <= 4; c4++)
-        for (int c3 = 0; c3 <= 5; c3++)
-            for (int c2 = 0; c2 <= 8; c2++)
-                for (int c1 = 0; c1 <= 16; c1++) {
-                    if (4 * c4 + 3 * c3 + 2 * c2 + c1 > 16) continue;
-                    const int nb = bl.nbins;
-                    if (nb * c4 < G[4] || nb * (c4 + c3) < G[4] + G[3] || nb * (c4 + c3 + c2) < G[4] + G[3] + G[2] ||
-                        nb * (c4 + c3 + c2 + c1) < G[4] + G[3] + G[2] + G[1])
-                        continue;
-                    const int slots = c4 + c3 + c2 + c1;
-                    if (slots < bestslots) {
-                        bestslots = slots;
-                        best[4] = c4, best[3] = c3, best[2] = c2, best[1] = c1;
-                    }
-                }
-    if (bestslots == (1 << 30)) return false;
+    // Every bin gets the same pattern of group slots (the kernel instance's
+    // constant pattern, largest groups first), so the group ends fall on the
+    // same accumulator slots in every lane and the per-output work never
+    // diverges.  Groups of size >= k need slots of size >= k.
+    const int ng = slot_groups(nrt);
+    if (ng == 0) return false;
     std::vector<int> pattern;  // slot sizes of one bin, largest first
-    for (int k = 4; k >= 1; k--)
-        for (int t = 0; t < best[k]; t++) pattern.push_back(k);
+    for (int g = 0; g < ng; g++) pattern.push_back(slot_group(nrt, g));
+    {
+        int tot = 0;
+        for (int k : pattern) tot += k;
+        if (tot > 16) return false;
+        std::vector<int> G(5, 0), cap(5, 0);
+        for (auto &g : groups) G[g.members.size()]++;
+        for (int k : pattern) cap[k] += bl.nbins;
+        int need = 0, have = 0;
+        for (int k = 4; k >= 1; k--) {
+            need += G[k];
+            have += cap[k];
+            if (have < need) return false;
+        }
+    }
     bl.slot_src.assign((size_t)bl.nbins * 16, -1);
     bl.slot.assign((size_t)bl.nbins * 16, 0);
     // group slots in order (slot position, bin): fill the largest groups first,

@@ -278,13 +278,13 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma(DevFamily fam, const D
                     int8_t *xp = X + c * XS + col;
 #pragma unroll
                     for (int j = 0; j < DS; j++) {
-                        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
+                        const uint32_t qd = __umulhi(vl, magic) >> shift;
                         xp[j * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
                         vl = qd;
                     }
 #pragma unroll
                     for (int j = DS; j < D; j++) {
-                        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
+                        const uint32_t qd = __umulhi(vh, magic) >> shift;
                         xp[j * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
                         vh = qd;
                     }
@@ -375,13 +375,13 @@ __device__ __forceinline__ static void put_digits(int8_t *xp, double x, double Q
     uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
 #pragma unroll
     for (int jd = 0; jd < DS; jd++) {
-        const uint32_t qd = (uint32_t)(((uint64_t)vl * magic) >> shift);
+        const uint32_t qd = __umulhi(vl, magic) >> shift;
         xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
         vl = qd;
     }
 #pragma unroll
     for (int jd = DS; jd < D; jd++) {
-        const uint32_t qd = (uint32_t)(((uint64_t)vh * magic) >> shift);
+        const uint32_t qd = __umulhi(vh, magic) >> shift;
         xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
         vh = qd;
     }
@@ -536,33 +536,42 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
         __syncthreads();  // every wave has read the current digit planes
         if (act) {
             const int16_t *cm = colmapL + dirn * s;
-            int zi[D];
-            double zd[D];
+            // the lane's slots in groups of the constant pattern: accumulate the
+            // weighted digit sums of a group, then finish its output r
+            int j0 = 0;
 #pragma unroll
-            for (int k = 0; k < D; k++) {
-                zi[k] = 0;
-                zd[k] = 0.0;
-            }
+            for (int g = 0; g < slot_groups(NRT); g++) {
+                const int gs = slot_group(NRT, g);
+                int zi[D];
+                double zd[D];
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t w = sl[j];
-                if (!(w & 1u)) continue;
-                const int iv = (w >> 2) & 7;
-                int ui = up[0];
-#pragma unroll
-                for (int i = 1; i < NV; i++) ui = (iv == i) ? up[i] : ui;
-                const int wt = ui + (int)((w >> 5) & 2047u);
-                if (Z32) {
-#pragma unroll
-                    for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < D; k++) zd[k] = fma((double)wt, (double)acc[k][j], zd[k]);
+                for (int k = 0; k < D; k++) {
+                    zi[k] = 0;
+                    zd[k] = 0.0;
                 }
-                if (!(w & 2u)) continue;
+                uint32_t wend = 0;
+#pragma unroll
+                for (int m = 0; m < 4; m++) {
+                    if (m >= gs) break;
+                    const int j = j0 + m;
+                    const uint32_t w = sl[j];
+                    wend = w;
+                    const int iv = (w >> 2) & 7;
+                    int ui = up[0];
+#pragma unroll
+                    for (int i = 1; i < NV; i++) ui = (iv == i) ? up[i] : ui;
+                    const int wt = (w & 1u) ? ui + (int)((w >> 5) & 2047u) : 0;  // 0 for an empty position
+                    if (Z32) {
+#pragma unroll
+                        for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < D; k++) zd[k] = fma((double)wt, (double)acc[k][j], zd[k]);
+                    }
+                }
+                j0 += gs;
                 // output r complete: w'[r] = sum_k Z_k B^k mod Q'
-                const int r = (int)(w >> 16);
-                if (r == 0xFFFF) continue;  // unused group slot
+                const int r = (int)(wend >> 16);
                 constexpr int H = D / 2;  // Horner split (host checks both halves stay exact)
                 double lo = 0.0, hi = 0.0;
 #pragma unroll
@@ -570,26 +579,26 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
                     const double zk = Z32 ? (double)zi[k] : zd[k];
                     if (k >= H) hi = fma(hi, Bd, zk);
                     else lo = fma(lo, Bd, zk);
-                    zi[k] = 0;
-                    zd[k] = 0.0;
                 }
                 double x = mod_fp(lo, Qd, invQ);
                 x = fma(mod_fp(hi, BHd, invBH), Bh, x);
                 if (x >= Qd) x -= Qd;
-                if (x == 0.0) continue;
+                if (r == 0xFFFF) continue;  // unused group slot
                 if (more) {
                     const int col = cm[r];
                     if (col < 0) {
-                        atomicOr(err, 2);
+                        if (x != 0.0) atomicOr(err, 2);
                         continue;
                     }
                     put_digits<D, XS>(Xn + c * XS + col, x, Qd, bias, Bsplit, invBsplit, magic, shift, Bi, halfB);
-                } else if (vout >= 0) {
-                    store[(size_t)vout * s + r] = (uint64_t)mod_fp(x, qd, invq);  // combine point
-                } else if (fin_row >= 0) {
-                    const int f = fam.finmap[fin_row + r];
-                    if (f < 0) atomicOr(err, 4);
-                    else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)mod_fp(x, qd, invq);
+                } else if (x != 0.0) {
+                    if (vout >= 0) {
+                        store[(size_t)vout * s + r] = (uint64_t)mod_fp(x, qd, invq);  // combine point
+                    } else if (fin_row >= 0) {
+                        const int f = fam.finmap[fin_row + r];
+                        if (f < 0) atomicOr(err, 4);
+                        else hbuf[(size_t)(tile.chain0 + c) * F + f] = (uint64_t)mod_fp(x, qd, invq);
+                    }
                 }
             }
         }
