@@ -136,7 +136,7 @@ def main():
     for _ in range(args.warmup):
         C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
     torch.cuda.synchronize()
-    tot = {"reduce_ms": 0.0, "combine_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
+    tot = {"reduce_ms": 0.0, "combine_ms": 0.0, "psi_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)

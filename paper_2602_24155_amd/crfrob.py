@@ -51,7 +51,7 @@ class cr_stats(ctypes.Structure):
                 ("assemble_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("engine", ctypes.c_int32), ("policy", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
-                ("reduce_launches", ctypes.c_int64)]
+                ("reduce_launches", ctypes.c_int64), ("psi_ms", ctypes.c_double)]
 
 
 class CrError(RuntimeError):

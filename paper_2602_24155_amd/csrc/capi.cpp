@@ -40,6 +40,10 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
                                uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
                                int pgrid, int *queue, hipStream_t stream);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t stream);
+size_t psi_lds_bytes(int R, int C);
+hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, hipStream_t stream);
+hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
+                           int nrt, int nkb, int T, int nsrc, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
 }  // namespace crf
 
@@ -100,7 +104,7 @@ struct Arena {
 struct FamilyEntry {
     Family fam;
     std::vector<unsigned char> tables;  // packed device tables (host copy)
-    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots;
+    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src;
     BinLayout bl;  // source-row placement for the register-gather MFMA kernel
     bool bl_ok = false;
 };
@@ -109,6 +113,7 @@ std::mutex g_mutex;
 Arena g_arenas[2];  // alternate between consecutive sub-batches of a call
 std::map<std::string, hipGraphExec_t> g_graphs;  // captured reduction launches by launch signature
 hipStream_t g_capture = nullptr;                 // private stream used for graph capture
+hipStream_t g_aux = nullptr;                     // upload and psi of the next sub-batch
 
 void clear_graphs() {
     for (auto &g : g_graphs) (void)hipGraphExecDestroy(g.second);
@@ -150,6 +155,9 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         e->bl_ok = mfma4_shape(shape, nrt, nkb) && bin_layout(F, nrt, e->bl);
         if (!e->bl_ok) e->bl.slot.assign(16, 0);
         e->off_slots = put(e->bl.slot.data(), e->bl.slot.size() * 4);
+        std::vector<int16_t> ss(e->bl.slot_src.begin(), e->bl.slot_src.end());
+        if (ss.empty()) ss.assign(16, -1);
+        e->off_slot_src = put(ss.data(), ss.size() * 2);
     }
     auto *raw = e.get();
     g_families.emplace(key, std::move(e));
@@ -375,6 +383,7 @@ struct BatchCtx {
     DevFamily df{};
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
+    bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     hipStream_t stream = nullptr;
     const int32_t *primes = nullptr;
     const uint32_t *coeffs = nullptr;
@@ -411,6 +420,8 @@ struct BatchCtx {
         use_bins = f->engine == 0 && fe->bl_ok;
         want_mfma = (f->engine == 0 || f->engine == 2) &&
                     (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
+        // the LDS-gather kernel (engine 2) keeps host psi and host packing
+        device_psi = f->engine != 2 && psi_lds_bytes(F->tgt.count, F->nsrc) <= 150 * 1024;
         return true;
     }
 };
@@ -434,13 +445,14 @@ struct SubBatch {
     std::vector<size_t> comb_first, comb_count;
     size_t h_end = 0, o_items = 0, o_tiles = 0, o_ditems = 0, o_tables = 0, o_cu = 0, o_cg = 0, o_cp = 0, o_vx = 0;
     size_t o_comb = 0, o_msrc = 0, o_malpha = 0, o_err = 0, o_Y = 0, o_hbuf = 0, o_store = 0, o_queue = 0;
+    size_t o_psi_dev = 0;
     DevFamily df{};
-    hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr, edone = nullptr;
+    hipEvent_t ep = nullptr, epe = nullptr, e0 = nullptr, em = nullptr, e1 = nullptr, edone = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
     double setup_ms = 0, finish_ms = 0;
-    float dev_ms = 0, red_ms = 0, asm_ms = 0, comb_ms = 0;
+    float dev_ms = 0, red_ms = 0, asm_ms = 0, comb_ms = 0, psi_ms = 0;
     void destroy_events() {
-        for (hipEvent_t *e : {&e0, &em, &e1, &edone})
+        for (hipEvent_t *e : {&ep, &epe, &e0, &em, &e1, &edone})
             if (*e) {
                 (void)hipEventDestroy(*e);
                 *e = nullptr;
@@ -469,7 +481,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     parallel_for(count, [&](int i) {
         const int g = sb.idx[i];
         sb.st[i] = setup_item(F, ctx.primes[g], ctx.coeffs + (size_t)g * ctx.nco, fam->r, fam->n_series,
-                              sb.items[i], sb.errs[i]);
+                              sb.items[i], sb.errs[i], false, !ctx.device_psi);
         if (sb.st[i] == CR_OK && sb.items[i].b != b) {
             sb.st[i] = CR_ESELFCHECK;
             sb.errs[i] = "basis size differs from the Hodge numbers";
@@ -485,7 +497,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, sb.dps[i]) &&
                 mfma_supports_digits(sb.dps[i].D)) {
                 it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
-                pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), ctx.use_bins ? &ctx.fe->bl : nullptr);
+                if (!ctx.device_psi)
+                    pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), ctx.use_bins ? &ctx.fe->bl : nullptr);
                 sb.digit_ok[i] = 1;
             }
         }
@@ -505,6 +518,10 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
     if (sb.use_mfma && !sb.use_bins && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
+    if (sb.use_mfma && !sb.use_bins && ctx.device_psi) sb.use_mfma = false;  // device packing follows the bin layout
+    if (!sb.use_mfma && ctx.device_psi && ctx.want_mfma) {
+        // an item the MFMA kernel cannot take: the VALU kernel reads psi from k_psi directly
+    }
     sb.ct = 32;
     if (!sb.use_mfma) {
         while (sb.ct > 1 && reduce_lds_bytes(df, sb.ct) > 64 * 1024) sb.ct /= 2;
@@ -589,11 +606,14 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     sb.o_tables = take(fe->tables.size());
     sb.o_items = take(sizeof(DevItem) * nlive);
     sb.o_tiles = take(sizeof(DevTile) * std::max<size_t>(tiles.size(), 1));
-    const size_t o_psi = take(sb.use_mfma ? 0 : 8 * psi_len * nlive);
+    const bool dpsi = ctx.device_psi;
+    const size_t o_psi = take(sb.use_mfma || dpsi ? 0 : 8 * psi_len * nlive);
     if (sb.use_mfma) {
         sb.o_ditems = take(sizeof(DevDigitItem) * nlive);
-        for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
+        if (!dpsi)
+            for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     }
+    const size_t o_J = take(dpsi ? 8 * psi_len * nlive : 0);
     const size_t o_rho = take(8 * rho_len * nlive);
     const size_t o_coef = take(8 * ncoef);
     sb.o_cu = take(2 * (size_t)F.nv * nvec);
@@ -605,8 +625,11 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     sb.o_malpha = take(8 * std::max<size_t>(nmem, 1));
     const size_t o_fvec = take(4 * std::max<size_t>(nfin_all, 1));
     const size_t o_frow = take(4 * std::max<size_t>(nfin_all, 1));
-    sb.o_err = take(4);
+    sb.o_err = take(4 * (1 + (size_t)nlive));  // error bits, then one k_psi flag per item
     sb.h_end = off;  // everything above is uploaded
+    sb.o_psi_dev = take(dpsi ? 8 * psi_len * nlive : 0);
+    if (sb.use_mfma && dpsi)
+        for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     sb.o_queue = take(4 * std::max<size_t>(sb.launches.size(), 1));
     sb.o_Y = take(8 * (size_t)b * b * nlive);
     const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
@@ -674,7 +697,16 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         di.sbits = it.mq.sbits;
         di.b = b;
         di.nchain = it.nchain();
-        di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
+        di.p = it.p;
+        di.flag = reinterpret_cast<int32_t *>(db + sb.o_err) + 1 + li;
+        if (dpsi) {
+            di.J = reinterpret_cast<const uint64_t *>(db + o_J) + psi_len * li;
+            di.psi_out = reinterpret_cast<uint64_t *>(db + sb.o_psi_dev) + psi_len * li;
+            di.psi = di.psi_out;
+            std::memcpy(hb + o_J + 8 * psi_len * li, it.J.data(), 8 * psi_len);
+        } else {
+            di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
+        }
         di.rho = reinterpret_cast<const uint64_t *>(db + o_rho) + rho_len * li;
         di.coef = reinterpret_cast<const uint64_t *>(db + o_coef) + coef0[li];
         di.Y = reinterpret_cast<uint64_t *>(db + sb.o_Y) + (size_t)b * b * li;
@@ -731,14 +763,15 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             dd.chain0 = 0;
             dd.nchain = it.nchain();
             dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
-            std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
-        } else {
+            dd.apack_out = reinterpret_cast<int8_t *>(db + apack_off[li]);
+            if (!dpsi) std::memcpy(hb + apack_off[li], it.apack.data(), it.apack.size());
+        } else if (!dpsi) {
             std::memcpy(hb + o_psi + 8 * psi_len * li, it.psi.data(), 8 * psi_len);
         }
         std::memcpy(hb + o_rho + 8 * rho_len * li, it.rho.data(), 8 * rho_len);
     });
     std::memcpy(hb + sb.o_tiles, tiles.data(), sizeof(DevTile) * tiles.size());
-    std::memset(hb + sb.o_err, 0, 4);
+    std::memset(hb + sb.o_err, 0, 4 * (1 + (size_t)nlive));
     sb.setup_ms = ms_since(t0);
     return CR_OK;
 }
@@ -757,7 +790,28 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     (void)hipEventCreate(&sb.e1);
     (void)hipEventCreate(&sb.em);
     (void)hipEventCreateWithFlags(&sb.edone, hipEventDisableTiming);
-    hipError_t he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
+    hipError_t he = hipSuccess;
+    if (ctx.device_psi) {
+        // upload, psi of every item and (MFMA path) its digits in the kernel's
+        // fragment order on the auxiliary stream: this overlaps the reduction of
+        // the previous sub-batch (whose arena is the other one); the main stream
+        // waits for it before the reductions
+        if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
+        (void)hipEventCreate(&sb.ep);
+        (void)hipEventCreate(&sb.epe);
+        if (he == hipSuccess) he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, g_aux);
+        (void)hipEventRecord(sb.ep, g_aux);
+        const DevItem *dv = reinterpret_cast<const DevItem *>(db + sb.o_items);
+        if (he == hipSuccess) he = launch_psi(dv, nlive, ctx.F->tgt.count, ctx.F->nsrc, g_aux);
+        if (he == hipSuccess && sb.use_mfma)
+            he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
+                                 reinterpret_cast<const int16_t *>(db + sb.o_tables + ctx.fe->off_slot_src), ctx.nrt,
+                                 ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, g_aux);
+        (void)hipEventRecord(sb.epe, g_aux);
+        if (he == hipSuccess) he = hipStreamWaitEvent(stream, sb.epe, 0);
+    } else {
+        he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
+    }
     (void)hipEventRecord(sb.e0, stream);
     const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + sb.o_items);
     const int16_t *cu = reinterpret_cast<const int16_t *>(db + sb.o_cu);
@@ -849,7 +903,8 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     (void)hipEventRecord(sb.e1, stream);
     if (he == hipSuccess)
         he = hipMemcpyAsync(hb + sb.o_Y, db + sb.o_Y, 8 * (size_t)b * b * nlive, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(hb + sb.o_err, db + sb.o_err, 4, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(hb + sb.o_err, db + sb.o_err, 4 * (1 + (size_t)nlive), hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipEventRecord(sb.edone, stream);
     if (he != hipSuccess) {
         msg = std::string("HIP error: ") + hipGetErrorString(he);
@@ -873,6 +928,7 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
         (void)hipEventElapsedTime(&sb.dev_ms, sb.e0, sb.e1);
         (void)hipEventElapsedTime(&sb.red_ms, sb.e0, sb.em);
         (void)hipEventElapsedTime(&sb.asm_ms, sb.em, sb.e1);
+        if (sb.ep) (void)hipEventElapsedTime(&sb.psi_ms, sb.ep, sb.epe);
         for (auto &ce : sb.cev) {
             float x = 0;
             (void)hipEventElapsedTime(&x, ce.first, ce.second);
@@ -891,12 +947,18 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
         msg = "device reduction invariant violated (code " + std::to_string(derr) + ")";
         return CR_ESELFCHECK;
     }
+    const int32_t *flags = reinterpret_cast<const int32_t *>(hb + sb.o_err) + 1;
     auto t2 = std::chrono::steady_clock::now();
     const uint64_t *Yh = reinterpret_cast<const uint64_t *>(hb + sb.o_Y);
     const Outputs &o = ctx.out;
     parallel_for((int)sb.live.size(), [&](int li) {
         const int i = sb.live[li], g = sb.idx[i];
         const size_t bb = (size_t)b * b;
+        if (flags[li]) {
+            st[g] = CR_ESINGULAR;
+            errs[g] = "J_S is not surjective mod p (no unit pivot)";
+            return;
+        }
         st[g] = finish_item(*ctx.F, sb.items[i], Yh + bb * li, o.frob + bb * g, o.col_pole + (size_t)b * g,
                             o.col_prec + (size_t)b * g, o.lpoly + (size_t)4 * (b + 1) * g, errs[g]);
         if (o.frob_scaled) std::memcpy(o.frob_scaled + bb * g, Yh + bb * li, 8 * bb);
@@ -1066,6 +1128,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     std::string fatal_msg;
     auto stop_all = [&](int upto) {  // drain the device before reporting a failure
         (void)hipStreamSynchronize(ctx.stream);
+        if (g_aux) (void)hipStreamSynchronize(g_aux);
         for (int k = 0; k <= upto && k < S; k++) sub[k].destroy_events();
     };
     for (int k = 0; k < S && fatal == CR_OK; k++) {
@@ -1102,7 +1165,8 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
                 stats->combined_groups += pl.combined_groups;
             }
             stats->setup_ms += sb.setup_ms;
-            stats->device_ms += sb.dev_ms;
+            stats->device_ms += sb.dev_ms + sb.psi_ms;
+            stats->psi_ms += sb.psi_ms;
             stats->reduce_ms += sb.red_ms - sb.comb_ms;
             stats->combine_ms += sb.comb_ms;
             stats->assemble_ms += sb.asm_ms;

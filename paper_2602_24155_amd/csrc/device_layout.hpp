@@ -31,7 +31,7 @@ struct DevItem {
     int32_t chain0;  // first chain (global index)
     int32_t nchain;
     int32_t nfin;    // vectors that reach pole n
-    int32_t pad_;
+    int32_t p;
     const uint64_t *psi;   // nsrc x T right inverse of J_S
     const uint64_t *rho;   // b x F Griffiths-Dwork coordinate map
     const uint64_t *coef;  // (nchain + b) x b: start coefficients, then the unit rows e_c
@@ -39,6 +39,9 @@ struct DevItem {
     const int32_t *frow;   // nfin: its coefficient row in coef
     uint64_t *Y;           // b x b output (coordinates, mod q)
     uint64_t *H;           // F x b scratch: summed pole-n numerators
+    const uint64_t *J;     // T x nsrc matrix of J_S mod q (input of k_psi)
+    uint64_t *psi_out;     // the psi buffer above, written by k_psi
+    int32_t *flag;         // set by k_psi when J_S has no unit pivot in some row
 };
 
 // Per reduced vector (one entry per vector of every phase of a plan).
@@ -90,6 +93,7 @@ struct DevDigitItem {
     int32_t z32;          // 1: the weighted digit sums fit int32
     int32_t chain0, nchain;
     const int8_t *apack;  // NRT x D x NKB x 64 lanes x 16 bytes: psi digits in MFMA A-fragment order
+    int8_t *apack_out;    // the same buffer, written by k_pack_psi
 };
 
 }  // namespace crf

@@ -434,7 +434,7 @@ static std::vector<long long> multiplier_matrix(const Family &fam, const std::ve
 }
 
 cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_override, int n_override,
-                     ItemSetup &out, std::string &err, bool smooth_only) {
+                     ItemSetup &out, std::string &err, bool smooth_only, bool host_psi) {
     const int nv = fam.nv, n = fam.n, d = fam.d;
     if (!is_prime(p)) {
         err = "p is not prime";
@@ -542,7 +542,10 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
     }
     const ModQ &mq = out.mq;
     // psi = right inverse of J_S over Z/q (Proposition 3.3 decomposition)
-    {
+    if (!host_psi) {
+        out.J.resize(J.size());
+        for (size_t k = 0; k < J.size(); k++) out.J[k] = mq.from_int(J[k]);
+    } else {
         std::vector<u64> Jq(J.size());
         for (size_t k = 0; k < J.size(); k++) Jq[k] = mq.from_int(J[k]);
         std::vector<u64> X;
@@ -671,14 +674,18 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                 }
             }
         }
-        struct KeyHash {
-            size_t operator()(const u128 &k) const { return (size_t)(k ^ (k >> 61) ^ (k >> 97)) * 0x9E3779B97F4A7C15ull; }
-        };
-        std::unordered_map<u128, int, KeyHash> where;
-        std::vector<std::array<int, kMaxVars>> Es;
-        std::vector<int> poles;
-        std::vector<u64> &coef = out.coef;
-        coef.clear();
+        // E' = p (gamma + 1) - 1 + 1_S with gamma = beta + alpha of degree d L - n - 1,
+        // L = m + j = P / p: one dense slot table per pole level, indexed by the
+        // rank of gamma (ranks run in lexicographically descending order)
+        const int nlev = n + N - 1;
+        std::vector<MonoSpace> lsp(nlev + 1);
+        std::vector<std::vector<int>> slot(nlev + 1);
+        for (int L = 1; L <= nlev; L++) {
+            lsp[L].init(nv, d * L - n - 1);
+            slot[L].assign(lsp[L].count, -1);
+        }
+        std::vector<int> lev_of, rank_of;  // per distinct start term
+        std::vector<u64> acc;              // nterm x b coefficients
         int col = 0;
         for (int m = 1; m <= n; m++) {
             const int sm = N + m - 1;
@@ -691,68 +698,61 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                     if (j & 1) Dj = -Dj;
                     i128 Dr = Dj % (i128)mq.q;
                     if (Dr < 0) Dr += (i128)mq.q;
-                    const int P = p * (m + j);
+                    const int P = p * (m + j), L = m + j;
                     u64 ratio = 1;  // (p s_m - 1)! / (P - 1)!
                     for (long long t = P; t <= (long long)p * sm - 1; t++) ratio = mq.mul(ratio, (u64)t % mq.q);
                     u64 scale = mq.mul((u64)Dr, ratio);
                     for (int a = 0; a < psp[j].count; a++) {
                         u64 C = fpow[j][a];
                         if (!C) continue;
-                        std::array<int, kMaxVars> E{};
-                        u128 key = 0;
-                        for (int i = 0; i < nv; i++) {
-                            E[i] = p * (beta[i] + psp[j].at(a)[i] + 1) - 1 + (int)((fam.smask >> i) & 1u);
-                            key = (key << 20) | (u128)E[i];
+                        for (int i = 0; i < nv; i++) e[i] = beta[i] + psp[j].at(a)[i];
+                        const int rk = lsp[L].rank(e);
+                        int &sl = slot[L][rk];
+                        if (sl < 0) {
+                            sl = (int)lev_of.size();
+                            lev_of.push_back(L);
+                            rank_of.push_back(rk);
+                            acc.resize(acc.size() + b, 0);
                         }
-                        auto it = where.find(key);
-                        int idx;
-                        if (it == where.end()) {
-                            idx = (int)Es.size();
-                            where.emplace(key, idx);
-                            Es.push_back(E);
-                            poles.push_back(P);
-                            coef.resize(coef.size() + b, 0);
-                        } else {
-                            idx = it->second;
-                        }
-                        u64 &slot = coef[(size_t)idx * b + col];
-                        slot = mq.add(slot, mq.mul(scale, C));
+                        u64 &v = acc[(size_t)sl * b + col];
+                        v = mq.add(v, mq.mul(scale, C));
                     }
                 }
             }
         }
-        // order chains by pole (descending), then exponent, for balanced tiles
-        std::vector<int> order(Es.size());
-        for (size_t k = 0; k < order.size(); k++) order[k] = (int)k;
-        std::sort(order.begin(), order.end(), [&](int x, int y) {
-            if (poles[x] != poles[y]) return poles[x] > poles[y];
-            return Es[x] > Es[y];
-        });
+        // chains ordered by pole (descending), then exponent (descending), for balanced tiles
         const int gdeg = d * n - n;
-        std::vector<u64> coef2((size_t)order.size() * b);
-        out.chain_u.resize(order.size() * nv);
-        out.chain_g.resize(order.size());
-        out.chain_pole.resize(order.size());
-        for (size_t k = 0; k < order.size(); k++) {
-            const auto &E = Es[order[k]];
-            // Algorithm 1 (Tweak): remove dn-n units from the front of E'
-            int left = gdeg, gam[kMaxVars];
-            for (int i = 0; i < nv; i++) {
-                int take = std::min(E[i], left);
-                gam[i] = take;
-                out.chain_u[k * nv + i] = (int16_t)(E[i] - take);
-                left -= take;
+        const size_t nterm = lev_of.size();
+        std::vector<u64> &coef = out.coef;
+        coef.assign(nterm * b, 0);
+        out.chain_u.resize(nterm * nv);
+        out.chain_g.resize(nterm);
+        out.chain_pole.resize(nterm);
+        size_t k = 0;
+        for (int L = nlev; L >= 1; L--)
+            for (int rk = 0; rk < lsp[L].count; rk++) {
+                const int sl = slot[L][rk];
+                if (sl < 0) continue;
+                const int8_t *gmono = lsp[L].at(rk);
+                // Algorithm 1 (Tweak): remove dn-n units from the front of E'
+                int left = gdeg, gam[kMaxVars];
+                for (int i = 0; i < nv; i++) {
+                    const int E = p * (gmono[i] + 1) - 1 + (int)((fam.smask >> i) & 1u);
+                    int take = std::min(E, left);
+                    gam[i] = take;
+                    out.chain_u[k * nv + i] = (int16_t)(E - take);
+                    left -= take;
+                }
+                out.chain_g[k] = fam.g.rank(gam);
+                if (out.chain_g[k] < 0) {
+                    err = "start term outside Homog_{dn-n} after Tweak";
+                    return CR_ESELFCHECK;
+                }
+                out.chain_pole[k] = p * L;
+                std::memcpy(&coef[k * b], &acc[(size_t)sl * b], sizeof(u64) * b);
+                out.column_steps += p * L - n;
+                k++;
             }
-            out.chain_g[k] = fam.g.rank(gam);
-            if (out.chain_g[k] < 0) {
-                err = "start term outside Homog_{dn-n} after Tweak";
-                return CR_ESELFCHECK;
-            }
-            out.chain_pole[k] = poles[order[k]];
-            std::memcpy(&coef2[k * b], &coef[(size_t)order[k] * b], sizeof(u64) * b);
-            out.column_steps += poles[order[k]] - n;
-        }
-        coef.swap(coef2);
     }
     // unscaling constants (Section 2.5): (p s_m - 1)!/(n-1)! = p^v * unit
     for (int c = 0; c < out.b; c++) {

@@ -91,7 +91,8 @@ struct ItemSetup {
     ModQ mq;
     std::vector<int> hodge;          // |B_m|, m = 1..n (index m-1)
     std::vector<int> col_pole;       // b
-    std::vector<u64> psi;            // nsrc x T, right inverse of J_S mod q
+    std::vector<u64> psi;            // nsrc x T, right inverse of J_S mod q (host_psi)
+    std::vector<u64> J;              // T x nsrc, J_S mod q (when psi is left to the device)
     std::vector<u64> rho;            // b x F, Griffiths-Dwork coordinates of pole-n numerators
     // start blocks (one chain each), sorted by pole descending
     std::vector<int16_t> chain_u;    // nchain x nv
@@ -111,8 +112,11 @@ bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_overrid
                       int &r, int &N, int &M, std::string &err);
 
 // S-smoothness test + full setup of one item.  Returns CR_OK or an error status.
+// With host_psi false the right inverse of J_S is not computed: out.J holds
+// J_S mod q for the device (k_psi), and a non-surjective J_S is reported there.
 cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_override,
-                     int n_override, ItemSetup &out, std::string &err, bool smooth_only = false);
+                     int n_override, ItemSetup &out, std::string &err, bool smooth_only = false,
+                     bool host_psi = true);
 
 // Unscale the device result Y (b x b mod q) and recover Q(T).
 cr_status finish_item(const Family &fam, const ItemSetup &it, const u64 *Y, u64 *frob,

@@ -1,0 +1,188 @@
+// Right inverse psi of J_S mod q = p^M on the device, and its int8 digits
+// for the MFMA reduction kernel (gfx950).
+//
+// psi is the decomposition map of Proposition 3.3: for a numerator h in the
+// target of J_S, psi h gives the g_i with h = sum_{i in S} g_i d_i f +
+// sum_{i not in S} g_i x_i d_i f.  One workgroup per hypersurface runs
+// Gauss-Jordan elimination on [J | I] (R = dim target rows, C = nsrc source
+// columns) in LDS: row r takes as pivot the first unused column whose entry is
+// a unit mod p (so every pivot is invertible mod p^M), scales the row by the
+// pivot's inverse (Fermat mod p, then Newton lifting y <- y (2 - a y) to
+// p^M) and clears the pivot column in every other row.  psi[c_r, :] is then
+// row r of the right half, and psi is zero on the non-pivot source rows.
+// A row without a unit pivot means J_S is not surjective mod p (f is not
+// S-smooth): the item's flag is set and its psi is left zero.
+#include <hip/hip_runtime.h>
+
+#include "device_layout.hpp"
+
+namespace crf {
+
+typedef unsigned __int128 u128p;
+
+struct PMod {
+    uint64_t q, mu;
+    int sbits;
+    __device__ __forceinline__ uint64_t reduce(u128p x) const {  // x < 2^(2 sbits + 8)
+        const uint64_t x1 = (uint64_t)(x >> (sbits - 1));
+        const uint64_t qh = (uint64_t)(((u128p)x1 * mu) >> (sbits + 9));
+        uint64_t r = (uint64_t)x - qh * q;
+        r = r >= q ? r - q : r;
+        r = r >= q ? r - q : r;
+        return r;
+    }
+    __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b) const { return reduce((u128p)a * b); }
+};
+
+// x mod p for a small p with 32-bit operations: x = hi 2^32 + lo
+__device__ __forceinline__ static uint32_t mod_small(uint64_t x, uint32_t p, uint32_t two32p) {
+    const uint32_t hi = (uint32_t)(x >> 32) % p, lo = (uint32_t)x % p;
+    return (hi * two32p + lo) % p;
+}
+
+// inverse of a unit a mod q = p^M
+__device__ static uint64_t inv_mod(const PMod &md, uint64_t a, uint32_t p, uint32_t two32p) {
+    const uint32_t a0 = mod_small(a, p, two32p);
+    uint32_t y0 = 1, base = a0, e = p - 2;  // a0^(p-2) mod p
+    while (e) {
+        if (e & 1) y0 = (y0 * base) % p;
+        base = (base * base) % p;
+        e >>= 1;
+    }
+    uint64_t y = y0;
+    // each step doubles the number of correct p-adic digits (7 steps reach p^128)
+    for (int it = 0; it < 7; it++) {
+        const uint64_t ay = md.mul(a, y);
+        const uint64_t t = ay <= 2 ? 2 - ay : 2 + md.q - ay;  // 2 - a y mod q
+        const uint64_t y2 = md.mul(y, t);
+        if (y2 == y) break;
+        y = y2;
+    }
+    return y;
+}
+
+// 256 threads of <= 64 VGPRs: a workgroup fits beside a reduction workgroup
+// on the same CU, so psi of the next sub-batch runs in the reduction's shadow
+constexpr int kPsiThreads = 256;
+constexpr int kPsiWaves = kPsiThreads / 64;
+
+// LDS: [J | I] (R x (C + R) u64), the pivot column snapshot (R u64), the
+// pivot inverse (u64), the pivot marks of the columns (C int), 8 int of scratch
+size_t psi_lds_bytes(int R, int C) { return (size_t)R * (C + R) * 8 + (size_t)(R + 1) * 8 + (size_t)C * 4 + 32; }
+
+__global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__ items, int R, int C) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const DevItem it = items[blockIdx.x];
+    const PMod md{it.q, it.mu, it.sbits};
+    const uint32_t p = (uint32_t)it.p, two32p = (uint32_t)((1ull << 32) % p);
+    const int W = C + R, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *a = reinterpret_cast<uint64_t *>(lds);
+    uint64_t *fcol = a + (size_t)R * W;
+    uint64_t *shinv = fcol + R;
+    int *used = reinterpret_cast<int *>(shinv + 1);
+    int *sh = used + C;  // sh[0]: pivot column, sh[1]: failure
+    for (int r = wave; r < R; r += kPsiWaves)
+        for (int k = lane; k < W; k += 64)
+            a[(size_t)r * W + k] = k < C ? it.J[(size_t)r * C + k] : (uint64_t)(k - C == r);
+    for (int k = tid; k < C; k += kPsiThreads) used[k] = 0;
+    if (tid == 0) sh[1] = 0;
+    __syncthreads();
+    for (int r = 0; r < R; r++) {
+        uint64_t *row = a + (size_t)r * W;
+        if (wave == 0) {
+            // first unused column holding a unit mod p (columns k = lane + 64 j)
+            int c = C;
+            for (int k0 = 0; k0 < C && c == C; k0 += 64) {
+                const int k = k0 + lane;
+                const bool ok = k < C && !used[k] && mod_small(row[k], p, two32p) != 0;
+                const unsigned long long m = __ballot(ok);
+                if (m) c = k0 + __ffsll((long long)m) - 1;
+            }
+            if (lane == 0) {
+                sh[0] = c;
+                if (c == C) sh[1] = 1;
+                else shinv[0] = inv_mod(md, row[c], p, two32p);
+            }
+        }
+        __syncthreads();
+        const int c = sh[0];
+        if (c == C) break;  // uniform: every thread read the same sh[0]
+        const uint64_t inv = shinv[0];
+        for (int k = tid; k < W; k += kPsiThreads) row[k] = md.mul(row[k], inv);
+        for (int r2 = tid; r2 < R; r2 += kPsiThreads) fcol[r2] = r2 == r ? 0 : a[(size_t)r2 * W + c];
+        __syncthreads();
+        // clear column c: each wave takes whole rows, skipping those already zero there
+        for (int r2 = wave; r2 < R; r2 += kPsiWaves) {
+            const uint64_t f = fcol[r2];
+            if (f == 0) continue;
+            uint64_t *o = a + (size_t)r2 * W;
+            for (int k = lane; k < W; k += 64) {
+                const uint64_t t = md.mul(f, row[k]);
+                const uint64_t x = o[k];
+                o[k] = x >= t ? x - t : x + md.q - t;
+            }
+        }
+        if (tid == 0) used[c] = r + 1;  // pivot of row r (1-based)
+        __syncthreads();
+    }
+    const bool fail = sh[1] != 0;
+    if (tid == 0 && fail) atomicOr(it.flag, 1);
+    // psi (C x R): row c = pivot of row r -> right half of row r
+    for (int cc = wave; cc < C; cc += kPsiWaves) {
+        const int r1 = used[cc];
+        for (int j = lane; j < R; j += 64)
+            it.psi_out[(size_t)cc * R + j] = (!fail && r1 > 0) ? a[(size_t)(r1 - 1) * W + C + j] : 0;
+    }
+}
+
+// Balanced base-B digits of psi in v_mfma_i32_32x32x32_i8 A-fragment order,
+// source rows placed by the bin layout:
+// apack[(((rt*D + i)*nkb + kb)*64 + lane)*16 + jj] = digit i of
+// psi[slot_src(2 rt + (lane%32 >> 2 & 1), (lane%32 >> 3) * 4 + lane%4)][32 kb + (lane/32)*16 + jj].
+__global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ items,
+                                                  const DevDigitItem *__restrict__ ditems,
+                                                  const int16_t *__restrict__ slot_src, int nrt, int nkb, int T,
+                                                  int nsrc) {
+    const DevItem it = items[blockIdx.y];
+    const DevDigitItem dd = ditems[blockIdx.y];
+    const int D = dd.D;
+    const int n = nrt * nkb * 64 * 16;  // entries per digit plane
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const int jj = e & 15, lane = (e >> 4) & 63, rest = e >> 10;
+    const int kb = rest % nkb, rt = rest / nkb;
+    const int rho = lane & 31, hh = (rho >> 2) & 1, js = (rho >> 3) * 4 + (rho & 3);
+    const int row = slot_src[(2 * rt + hh) * 16 + js];
+    const int k = 32 * kb + (lane >> 5) * 16 + jj;
+    uint64_t x = (row >= 0 && row < nsrc && k < T) ? it.psi_out[(size_t)row * T + k] : 0;
+    // balanced digits of x = unsigned digits of (x + (Q'-1)/2) mod Q', minus (B-1)/2
+    const uint64_t Q = dd.Qp, bias = (Q - 1) / 2, B = (uint64_t)dd.B;
+    x += bias;
+    if (x >= Q) x -= Q;
+    int8_t *out = dd.apack_out + ((size_t)(rt * D) * nkb + kb) * 1024 + (size_t)lane * 16 + jj;
+    for (int i = 0; i < D; i++) {
+        const uint64_t qd = x / B;
+        out[(size_t)i * nkb * 1024] = (int8_t)((int)(x - qd * B) - dd.halfB);
+        x = qd;
+    }
+}
+
+hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, hipStream_t stream) {
+    if (nitems == 0) return hipSuccess;
+    const size_t lds = psi_lds_bytes(R, C);
+    hipError_t e = hipFuncSetAttribute((const void *)k_psi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_psi, dim3(nitems), dim3(kPsiThreads), lds, stream, items, R, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
+                           int nrt, int nkb, int T, int nsrc, hipStream_t stream) {
+    if (nitems == 0) return hipSuccess;
+    const int n = nrt * nkb * 64 * 16;
+    hipLaunchKernelGGL(k_pack_psi, dim3((n + 255) / 256, nitems), dim3(256), 0, stream, items, ditems, slot_src, nrt,
+                       nkb, T, nsrc);
+    return hipGetLastError();
+}
+
+}  // namespace crf

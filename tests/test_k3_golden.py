@@ -1,0 +1,65 @@
+"""Random quartic K3 surfaces (config 3): stored oracle results.
+
+tests/golden/k3_golden.json is written by tests/golden/make_k3_golden.py,
+which calls only oracle/ (about a minute per surface).  On the CPU the stored
+L-polynomials are checked against facts independent of the oracle (Weil
+bounds and the functional equation, #X(F_p) by brute force, the inputs being
+the workload's); on the GPU the library is compared with them bit for bit,
+under every policy.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.lpoly import point_counts_from_lpoly, weil_root_check
+from oracle.poly import from_coeffs
+from oracle.pointcount import count_projective
+from paper_2602_24155_amd import crfrob as C
+from paper_2602_24155_amd import workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "k3_golden.json")
+
+
+def golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)["items"]
+
+
+def test_golden_inputs_are_the_workload_items():
+    for it in golden():
+        p, c = workload.first_accepted("quartic_k3_mixed", it["j"], lambda p_, c_: True)
+        assert p == it["p"]
+        # the stored candidate is one of the stream's candidates (the first smooth one)
+        _p, gen = workload.stream("quartic_k3_mixed", it["j"])
+        assert any(next(gen) == it["coeffs"] for _ in range(64))
+    assert sorted(it["p"] for it in golden()) == [7, 11, 13]
+
+
+def test_golden_lpolys_satisfy_weil_and_point_counts():
+    for it in golden():
+        p = it["p"]
+        a = [int(x) for x in it["lpoly"]]
+        assert len(a) == 22 and a[0] == 1 and abs(a[21]) == p ** 21
+        assert weil_root_check(a, p, 2)
+        f = {e: v % p for e, v in from_coeffs(4, 4, it["coeffs"]).items() if v % p}
+        assert point_counts_from_lpoly(a, p, 3, 1) == [count_projective(f, 4, p, 1)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("policy", [C.CR_POLICY_DEPTH_FIRST, C.CR_POLICY_P_CHUNK, C.CR_POLICY_VAR_BY_VAR])
+def test_gpu_matches_golden(policy):
+    items = golden()
+    fam = C.family(4, 4, policy=policy)
+    res = C.cr_frobenius_batch(fam, [it["p"] for it in items], [it["coeffs"] for it in items])
+    assert res["stats"].policy == policy
+    for i, it in enumerate(items):
+        assert res["item_status"][i] == 0
+        assert [[int(x) for x in row] for row in res["scaled"][i]] == [[int(x) for x in row] for row in it["scaled"]]
+        assert [int(x) for x in res["col_pole"][i]] == it["col_pole"]
+        assert [int(x) for x in res["col_prec"][i]] == it["col_prec"]
+        prec = it["col_prec"]
+        want = [[int(x) % it["p"] ** prec[c_] for c_, x in enumerate(row)] for row in it["phi_prime"]]
+        assert [[int(x) for x in row] for row in res["frob"][i]] == want
+        assert res["lpoly"][i] == [int(x) for x in it["lpoly"]]
