@@ -100,14 +100,23 @@ struct DevDigitItem {
 
 namespace crf {
 
-// Lane-slot pattern of the register-gather kernel: the sizes of the output
-// groups held by one lane bin, the same in every bin (a group is the set of
-// source rows src(r, i) that feed output r; its rows sit at the end of its
-// slot, so the group ends on a fixed accumulator slot).  Quartic curves
-// (2 row tiles, 4 bins) and quintic curves (4 row tiles, 8 bins).
-constexpr int kSlotGroups2[] = {3, 3, 3, 1, 1, 1, 1};
+// Lane-slot pattern of the register-gather kernel: the output groups held by
+// one lane bin, the same in every bin (a group is the set of source rows
+// src(r, i) that feed output r, stored at the group's slots in the order of
+// i).  For S = all variables in three variables a group has all three
+// variables (r_i >= 1 for every i) or exactly one, the variable z with
+// r_z = 0.  Each one-row slot position is reserved for one variable, so the
+// variable of every slot is a constant of the pattern; empty slots hold
+// zero rows of psi and contribute nothing.  Quartic curves (2 row tiles,
+// 4 bins, two one-row slots per variable) and quintic curves (4 row tiles,
+// 8 bins, one per variable).
+constexpr int kSlotGroups2[] = {3, 3, 3, 1, 1, 1, 1, 1, 1};
+constexpr int kSlotVars2[] = {-1, -1, -1, 0, 1, 2, 0, 1, 2};
 constexpr int kSlotGroups4[] = {3, 3, 3, 1, 1, 1};
-constexpr int slot_groups(int nrt) { return nrt == 2 ? 7 : (nrt == 4 ? 6 : 0); }
+constexpr int kSlotVars4[] = {-1, -1, -1, 0, 1, 2};
+constexpr int slot_groups(int nrt) { return nrt == 2 ? 9 : (nrt == 4 ? 6 : 0); }
 constexpr int slot_group(int nrt, int g) { return nrt == 2 ? kSlotGroups2[g] : kSlotGroups4[g]; }
+// variable of a one-row group (-1 for a three-row group: variables 0, 1, 2 in order)
+constexpr int slot_var(int nrt, int g) { return nrt == 2 ? kSlotVars2[g] : kSlotVars4[g]; }
 
 }  // namespace crf

@@ -859,52 +859,41 @@ bool bin_layout(const Family &fam, int nrt, BinLayout &bl) {
     }
     if (maxsz > 4) return false;
     bl.nbins = 2 * nrt;
-    // Every bin gets the same pattern of group slots (the kernel instance's
-    // constant pattern, largest groups first), so the group ends fall on the
-    // same accumulator slots in every lane and the per-output work never
-    // diverges.  Groups of size >= k need slots of size >= k.
+    // Every bin gets the kernel instance's constant pattern of group slots:
+    // three-row groups (variables 0, 1, 2 in order) in the three-row slots,
+    // one-row groups of variable z in the one-row slots reserved for z, spread
+    // round-robin over the bins.  Anything else falls back to another kernel.
     const int ng = slot_groups(nrt);
-    if (ng == 0) return false;
-    std::vector<int> pattern;  // slot sizes of one bin, largest first
-    for (int g = 0; g < ng; g++) pattern.push_back(slot_group(nrt, g));
-    {
-        int tot = 0;
-        for (int k : pattern) tot += k;
-        if (tot > 16) return false;
-        std::vector<int> G(5, 0), cap(5, 0);
-        for (auto &g : groups) G[g.members.size()]++;
-        for (int k : pattern) cap[k] += bl.nbins;
-        int need = 0, have = 0;
-        for (int k = 4; k >= 1; k--) {
-            need += G[k];
-            have += cap[k];
-            if (have < need) return false;
-        }
-    }
-    bl.slot_src.assign((size_t)bl.nbins * 16, -1);
-    bl.slot.assign((size_t)bl.nbins * 16, 0);
-    // group slots in order (slot position, bin): fill the largest groups first,
-    // round-robin over bins so the outputs spread evenly across lanes
-    std::stable_sort(groups.begin(), groups.end(),
-                     [](const Group &a, const Group &b) { return a.members.size() > b.members.size(); });
+    if (ng == 0 || nv != 3) return false;
     struct Slot {
-        int bin, start, size;
+        int bin, start, size, var;
         bool used;
     };
     std::vector<Slot> slots;
-    for (size_t pi = 0, start = 0; pi < pattern.size(); start += pattern[pi], pi++)
-        for (int b = 0; b < bl.nbins; b++) slots.push_back({b, (int)start, pattern[pi], false});
+    {
+        int start = 0;
+        for (int g = 0; g < ng; g++) {
+            for (int b = 0; b < bl.nbins; b++) slots.push_back({b, start, slot_group(nrt, g), slot_var(nrt, g), false});
+            start += slot_group(nrt, g);
+        }
+        if (start > 16) return false;
+    }
+    bl.slot_src.assign((size_t)bl.nbins * 16, -1);
+    bl.slot.assign((size_t)bl.nbins * 16, 0);
     for (const Group &g : groups) {
         const int sz = (int)g.members.size();
+        const bool full = sz == 3 && g.members[0] == 0 && g.members[1] == 1 && g.members[2] == 2;
+        if (!full && sz != 1) return false;
         Slot *pick = nullptr;
-        for (auto &sl : slots)  // smallest free slot that holds the group
-            if (!sl.used && sl.size >= sz && (!pick || sl.size < pick->size)) pick = &sl;
+        for (auto &sl : slots)
+            if (!sl.used && sl.size == sz && (full || sl.var == g.members[0])) {
+                pick = &sl;
+                break;
+            }
         if (!pick) return false;
         pick->used = true;
-        // rows at the END of the slot so that the group end is the slot end
-        const int first = pick->start + pick->size - sz;
         for (int m = 0; m < sz; m++) {
-            const int i = g.members[m], j = first + m;
+            const int i = g.members[m], j = pick->start + m;
             const int src = fam.gsrc[(size_t)g.r * nv + i];
             const int gwv = fam.gw[(size_t)g.r * nv + i];
             bl.slot_src[(size_t)pick->bin * 16 + j] = src;

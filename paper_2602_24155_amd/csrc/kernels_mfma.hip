@@ -551,16 +551,14 @@ __device__ __forceinline__ static void mfma4_tile(const DevFamily &fam, const De
                 }
                 uint32_t wend = 0;
 #pragma unroll
-                for (int m = 0; m < 4; m++) {
+                for (int m = 0; m < 3; m++) {
                     if (m >= gs) break;
                     const int j = j0 + m;
                     const uint32_t w = sl[j];
                     wend = w;
-                    const int iv = (w >> 2) & 7;
-                    int ui = up[0];
-#pragma unroll
-                    for (int i = 1; i < NV; i++) ui = (iv == i) ? up[i] : ui;
-                    const int wt = (w & 1u) ? ui + (int)((w >> 5) & 2047u) : 0;  // 0 for an empty position
+                    // variable of the slot: m in a three-row group, the reserved z in a one-row group
+                    const int iv = slot_var(NRT, g) < 0 ? m : slot_var(NRT, g);
+                    const int wt = up[iv] + (int)((w >> 5) & 2047u);  // empty slots meet zero rows
                     if (Z32) {
 #pragma unroll
                         for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
