@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
-KERNEL_NAMES = {0: "k_reduce_mfma4", 1: "k_reduce_chains", 2: "k_reduce_mfma"}  # engine -> kernel (grid launch)
+KERNEL_NAMES = {0: "k_reduce_mfma5", 1: "k_reduce_chains", 2: "k_reduce_mfma", 3: "k_reduce_mfma4"}  # engine that ran
 
 
 def measured_traffic(kernel, workload):
@@ -159,7 +159,7 @@ def main():
     work_per_colstep = work / len(primes)
     red_s = tot["reduce_ms"] / 1e3 / args.steps
     achieved = st.column_steps * work_per_colstep / red_s / 1e12
-    kname = KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 0 and fam.launch > 0 else "")
+    kname = KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 3 and fam.launch > 0 else "")
     line = {
         "metric": "Frobenius matrices/sec (batched quintic curves, p=31) + modular matvecs/sec vs plain",
         "value": value,

@@ -92,9 +92,12 @@ typedef struct {
     int32_t r;        /* relative precision override; 0 = derive (header comment) */
     int32_t n_series; /* series order override N_m for every m; 0 = r + 1 */
     int32_t engine;   /* reduction kernel: 0 = auto (int8-digit MFMA kernel with the gather on
-                         the accumulators when the family's tables fit it, else the 64-bit VALU
-                         kernel), 1 = 64-bit VALU kernel, 2 = int8-digit MFMA kernel with the
-                         gather through LDS */
+                         the accumulators and two interleaved tiles per workgroup -- the
+                         products of one tile overlap the finishing of the other -- when the
+                         family and digit count allow it, else the same kernel with one tile per
+                         workgroup, else the 64-bit VALU kernel), 1 = 64-bit VALU kernel,
+                         2 = int8-digit MFMA kernel with the gather through LDS, 3 = register-
+                         gather MFMA kernel with one tile per workgroup */
     int32_t launch;   /* reduction launches (int8-digit register-gather kernel; the others always
                          use mode 0): 0 = one workgroup per tile of 32 vectors; 1 = persistent:
                          one grid sized to the device's resident capacity drains the tiles
@@ -119,7 +122,8 @@ typedef struct {
     double combine_ms;       /* device time of the combine kernels */
     double assemble_ms;      /* device time of the Griffiths-Dwork assembly kernel */
     double finish_ms;        /* host unscaling and L-polynomial recovery */
-    int32_t engine;          /* kernel that ran: 0 / 2 = int8-digit MFMA (register / LDS gather), 1 = 64-bit VALU */
+    int32_t engine;          /* kernel that ran: 0 / 3 / 2 = int8-digit MFMA (register gather with tile
+                                pairs / with one tile / LDS gather), 1 = 64-bit VALU */
     int32_t policy;          /* policy whose plan ran */
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
     int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a

@@ -105,7 +105,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS = 0, 1, 2
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS, ENGINE_MFMA_SINGLE = 0, 1, 2, 3
 
 
 LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2

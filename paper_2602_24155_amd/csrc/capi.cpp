@@ -40,6 +40,11 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
                                uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
                                int pgrid, int *queue, hipStream_t stream);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t stream);
+bool mfma5_supports(const DevFamily &fam, int D);
+hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int npairs,
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
+                               int pgrid, int *queue, hipStream_t stream);
 size_t psi_lds_bytes(int R, int C);
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, hipStream_t stream);
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
@@ -267,7 +272,7 @@ bool check_family(const cr_family *fam, std::string &err) {
         err = "unsupported nvars/degree";
         return false;
     }
-    if (fam->engine < 0 || fam->engine > 2) {
+    if (fam->engine < 0 || fam->engine > 3) {
         err = "unknown engine";
         return false;
     }
@@ -384,6 +389,7 @@ struct BatchCtx {
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
+    bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
     const int32_t *primes = nullptr;
     const uint32_t *coeffs = nullptr;
@@ -417,8 +423,9 @@ struct BatchCtx {
         df.nfinU = F->finU.count;
         policy = f->policy;
         // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
-        use_bins = f->engine == 0 && fe->bl_ok;
-        want_mfma = (f->engine == 0 || f->engine == 2) &&
+        use_bins = (f->engine == 0 || f->engine == 3) && fe->bl_ok;
+        pairs = f->engine == 0;  // engine 3: the single-tile kernel
+        want_mfma = (f->engine == 0 || f->engine == 2 || f->engine == 3) &&
                     (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
         // the LDS-gather kernel (engine 2) keeps host psi and host packing
         device_psi = f->engine != 2 && psi_lds_bytes(F->tgt.count, F->nsrc) <= 150 * 1024;
@@ -436,7 +443,7 @@ struct SubBatch {
     std::vector<DigitParams> dps;
     std::vector<char> digit_ok;
     std::vector<int> live;  // local indices of the items that reach the device
-    bool use_mfma = false, use_bins = false;
+    bool use_mfma = false, use_bins = false, use_pairs = false;
     int ct = 32, nphase = 0, fallbacks = 0;
     struct Launch {
         int phase, key, tile0, ntiles;
@@ -518,6 +525,9 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
     if (sb.use_mfma && !sb.use_bins && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
+    sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs;
+    for (int li = 0; li < nlive && sb.use_pairs; li++)
+        if (!mfma5_supports(df, sb.dps[sb.live[li]].D)) sb.use_pairs = false;
     if (sb.use_mfma && !sb.use_bins && ctx.device_psi) sb.use_mfma = false;  // device packing follows the bin layout
     if (!sb.use_mfma && ctx.device_psi && ctx.want_mfma) {
         // an item the MFMA kernel cannot take: the VALU kernel reads psi from k_psi directly
@@ -567,6 +577,34 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                     tiles.push_back(tl);
                 }
                 nvec += ph.size();
+            }
+            if (sb.use_pairs && (int)tiles.size() > first) {
+                // pairs of tiles of one item (an odd one out gets an empty partner),
+                // longest pairs first
+                std::vector<std::pair<DevTile, DevTile>> pr;
+                for (size_t k = first; k < tiles.size();) {
+                    DevTile a = tiles[k], b = a;
+                    b.count = 0;
+                    b.steps = 0;
+                    if (k + 1 < tiles.size() && tiles[k + 1].item == a.item) {
+                        b = tiles[k + 1];
+                        k += 2;
+                    } else {
+                        k += 1;
+                    }
+                    pr.push_back({a, b});
+                }
+                std::stable_sort(pr.begin(), pr.end(), [](const std::pair<DevTile, DevTile> &x,
+                                                          const std::pair<DevTile, DevTile> &y) {
+                    return std::max(x.first.steps, x.second.steps) > std::max(y.first.steps, y.second.steps);
+                });
+                tiles.resize(first);
+                for (auto &q : pr) {
+                    tiles.push_back(q.first);
+                    tiles.push_back(q.second);
+                }
+                sb.launches.push_back({t, key, first, (int)pr.size()});
+                continue;
             }
             // longest tiles first, so that the last wave of workgroups is short
             std::stable_sort(tiles.begin() + first, tiles.end(),
@@ -851,7 +889,11 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                     const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems);
                     const int Dg = L.key % 100;
                     const bool z32g = L.key >= 100;
-                    if (sb.use_bins)
+                    if (sb.use_pairs)
+                        e = launch_reduce_mfma5(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
+                                                reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
+                                                errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
+                    else if (sb.use_bins)
                         e = launch_reduce_mfma4(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
                                                 errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
@@ -1175,7 +1217,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             stats->reduce_launches += (int64_t)sb.launches.size();
             stats->fallbacks += sb.fallbacks;
             if (!sb.live.empty()) {
-                const int e = sb.use_mfma ? (sb.use_bins ? 0 : 2) : 1;
+                const int e = sb.use_mfma ? (sb.use_pairs ? 0 : (sb.use_bins ? 3 : 2)) : 1;
                 // a sub-batch that fell back to the VALU kernel makes the call report it
                 if (stats->engine < 0 || e == 1) stats->engine = e;
             }

@@ -690,6 +690,487 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// k_reduce_mfma5: the register-gather kernel with two tiles of one
+// hypersurface per workgroup, interleaved so that the matrix cores and the
+// vector ALUs work at the same time.  A step alternates two phases, each a
+// straight-line block closed by one barrier:
+//   phase 1: products of tile B (step t)   || finish of tile A (step t)
+//   phase 2: products of tile A (step t+1) || finish of tile B (step t)
+// The finish of a tile (weighted gather, exact recombination, digit split)
+// is branch-free: a digit that has nowhere to go is written to the pad
+// column of its plane row (never read by the products), and the outputs of a
+// chain that ends at this step are parked as 8-byte values in its own rows of
+// the next planes (which no later step of that chain reads), then written
+// out after the barrier.
+// Branch-free forms of mod_fp and put_digits (the corrections are added as
+// multiples of the flag), so that a whole finishing block is one basic block.
+__device__ __forceinline__ double mod_fp_nb(double x, double Q, double invQ) {
+    const double qt = floor(x * invQ);
+    double r = fma(-qt, Q, x);
+    r += Q * (double)(r < 0.0);
+    r -= Q * (double)(r >= Q);
+    return r;
+}
+
+template <int D, int XS>
+__device__ __forceinline__ static void put_digits_nb(int8_t *xp, double x, double Qd, double bias, double Bsplit,
+                                                     double invBsplit, uint32_t magic, int shift, int Bi, int halfB) {
+    constexpr int DS = (D + 1) / 2;
+    double xs = x + bias;
+    xs -= Qd * (double)(xs >= Qd);
+    double xh = floor(xs * invBsplit);
+    double rl = fma(-xh, Bsplit, xs);
+    const double lowf = (double)(rl < 0.0), highf = (double)(rl >= Bsplit);
+    rl += Bsplit * (lowf - highf);
+    xh += highf - lowf;
+    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
+#pragma unroll
+    for (int jd = 0; jd < DS; jd++) {
+        const uint32_t qd = __umulhi(vl, magic) >> shift;
+        xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
+        vl = qd;
+    }
+#pragma unroll
+    for (int jd = DS; jd < D; jd++) {
+        const uint32_t qd = __umulhi(vh, magic) >> shift;
+        xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
+        vh = qd;
+    }
+}
+
+template <int NV>
+struct TileState {
+    int U[NV], V[NV];
+    int dir, kleft, pole, pend, vout, fin_row;
+    bool act, more;
+    int up[NV], Vn[NV], dirn, kleftn;
+};
+
+template <int NRT, int NKB, int D, int NV>
+__device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, const DevDigitItem &it,
+                                  const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
+                                  const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
+                                  uint64_t *__restrict__ store, int *__restrict__ err, int8_t *X,
+                                  const int16_t *colmapL, const int8_t *dirsL, TileState<NV> &ts) {
+    constexpr int XS = NKB * 32 + 16;
+    const int s = fam.s, n = fam.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 31, half = lane >> 5, bin = 2 * wave + half;
+#pragma unroll
+    for (int i = 0; i < NV; i++) ts.U[i] = ts.V[i] = 0;
+    ts.dir = 0;
+    ts.kleft = 0;
+    ts.pole = n;
+    ts.pend = n;
+    ts.vout = -1;
+    if (c >= tile.count) return;
+    const int g = tile.chain0 + c;
+    const DevVec xv = vx[g];
+#pragma unroll
+    for (int i = 0; i < NV; i++) ts.U[i] = cu[(size_t)g * NV + i];
+    ts.pole = cpole[g];
+    ts.pend = xv.pend;
+    ts.vout = xv.out;
+    int d0, k0;
+    if (xv.dir >= 0) {
+        d0 = xv.dir;
+        k0 = ts.pole - ts.pend;
+#pragma unroll
+        for (int i = 0; i < NV; i++) ts.V[i] = dirsL[d0 * NV + i];
+    } else {
+        choose_chunk_reg<NV>(fam, dirsL, ts.U, ts.pole - ts.pend, ts.V, d0, k0);
+    }
+    if (d0 < 0 || k0 < 1) {
+        if (wave == 0 && half == 0) atomicOr(err, 1);
+        d0 = 0;
+        ts.pole = ts.pend;
+    }
+    ts.dir = d0;
+    ts.kleft = k0;
+    const double Qd = it.Qd, bias = it.bias, Bsplit = it.Bsplit, invBsplit = it.invBsplit;
+    if (xv.in < 0) {
+        if (wave == 0 && half == 0) {
+            const int col = colmapL[d0 * s + cg[g]];
+            if (col < 0) atomicOr(err, 2);
+            else X[c * XS + col] = (int8_t)1;  // balanced digits of 1
+        }
+    } else {
+        for (int r = bin; r < s; r += 2 * NRT) {
+            const uint64_t x = store[(size_t)xv.in * s + r];
+            if (x == 0) continue;
+            const int col = colmapL[d0 * s + r];
+            if (col < 0) {
+                atomicOr(err, 2);
+                continue;
+            }
+            put_digits<D, XS>(X + c * XS + col, (double)x, Qd, bias, Bsplit, invBsplit, it.magic, it.shift, it.B,
+                              it.halfB);
+        }
+    }
+}
+
+// exponent after the step, next direction and chunk, final-exponent row
+template <int NV>
+__device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const int8_t *dirsL, TileState<NV> &ts,
+                                                  int &bad) {
+    ts.act = ts.pole > ts.pend;
+    ts.dirn = ts.dir;
+    ts.kleftn = ts.kleft - 1;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        ts.up[i] = ts.U[i] - (ts.act ? ts.V[i] : 0);
+        ts.Vn[i] = ts.V[i];
+    }
+    ts.more = ts.act && ts.pole - 1 > ts.pend;
+    if (ts.more && ts.kleftn == 0) {
+        int d0, k0;
+        choose_chunk_reg<NV>(fam, dirsL, ts.up, ts.pole - 1 - ts.pend, ts.Vn, d0, k0);
+        if (d0 < 0 || k0 < 1) {
+            bad |= 1;
+            d0 = 0;
+            k0 = 1 << 30;
+        }
+        ts.dirn = d0;
+        ts.kleftn = k0;
+    }
+    ts.fin_row = -1;
+    if (ts.act && !ts.more && ts.vout < 0) {
+        int Ui = -1;
+        for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
+            bool eq = true;
+#pragma unroll
+            for (int i = 0; i < NV; i++) eq = eq && (fam.finU[a * NV + i] == ts.up[i]);
+            if (eq) Ui = a;
+        }
+        if (Ui < 0) bad |= 4;
+        else ts.fin_row = Ui * fam.s;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ static void mfma5_advance(TileState<NV> &ts) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        ts.U[i] = ts.up[i];
+        ts.V[i] = ts.Vn[i];
+    }
+    if (ts.act) {
+        ts.pole -= 1;
+        ts.dir = ts.dirn;
+        ts.kleft = ts.kleftn;
+    }
+}
+
+template <int NKB, int D>
+__device__ __forceinline__ static void mfma5_products(const v4i (&A)[D][NKB], const int8_t *Xc, int c, int half,
+                                                      v16i (&acc)[D]) {
+    constexpr int XS = NKB * 32 + 16;
+#pragma unroll
+    for (int k = 0; k < D; k++) acc[k] = v16i{0};
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        v4i xb[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; kb++)
+            xb[kb] = *reinterpret_cast<const v4i *>(Xc + (j * kCT + c) * XS + kb * 32 + half * 16);
+#pragma unroll
+        for (int i = 0; i + j < D; i++)
+#pragma unroll
+            for (int kb = 0; kb < NKB; kb++)
+                acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], acc[i + j], 0, 0, 0);
+    }
+}
+
+// Branch-free finish of output group g of one tile's step: digits of
+// continuing chains go to their columns of the next planes Xn, the 8-byte
+// outputs of ending chains to their own rows of Xn (slot r: plane r / (K/8),
+// column 8 (r mod (K/8))), everything else to the pad column K.
+template <int NRT, int NKB, int D, int NV, bool Z32, int G>
+__device__ __forceinline__ static void mfma5_finish_group(const v16i (&acc)[D], const uint32_t (&sl)[16],
+                                                          const TileState<NV> &ts, const int16_t *cm, int8_t *row,
+                                                          const DevDigitItem &it, int &bad) {
+    constexpr int K = NKB * 32;
+    constexpr int XS = K + 16;
+    constexpr int SPR = K / 8;  // 8-byte parking slots per plane row
+    constexpr int gs = slot_group(NRT, G);
+    constexpr int j0 = [] {
+        int t = 0;
+        for (int q = 0; q < G; q++) t += slot_group(NRT, q);
+        return t;
+    }();
+    const bool cont = ts.act && ts.more, ends = ts.act && !ts.more;
+    int zi[D];
+    double zd[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        zi[k] = 0;
+        zd[k] = 0.0;
+    }
+    uint32_t wend = 0;
+#pragma unroll
+    for (int m = 0; m < gs; m++) {
+        const int j = j0 + m;
+        const uint32_t w = sl[j];
+        wend = w;
+        const int iv = slot_var(NRT, G) < 0 ? m : slot_var(NRT, G);
+        const int wt = ts.up[iv] + (int)((w >> 5) & 2047u);
+        if (Z32) {
+#pragma unroll
+            for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; k++) zd[k] = fma((double)wt, (double)acc[k][j], zd[k]);
+        }
+    }
+    const int r = (int)(wend >> 16);
+    constexpr int H = D / 2;
+    double lo = 0.0, hi = 0.0;
+#pragma unroll
+    for (int k = D - 1; k >= 0; k--) {
+        const double zk = Z32 ? (double)zi[k] : zd[k];
+        if (k >= H) hi = fma(hi, it.Bd, zk);
+        else lo = fma(lo, it.Bd, zk);
+    }
+    const double Qd = it.Qd;
+    double x = mod_fp_nb(lo, Qd, it.invQ);
+    x = fma(mod_fp_nb(hi, it.BHd, it.invBH), it.Bh, x);
+    x -= Qd * (double)(x >= Qd);
+    const bool rv = r != 0xFFFF;
+    const int col = cm[rv ? r : 0];
+    const bool put = cont && rv && col >= 0;
+    bad |= (cont && rv && col < 0 && x != 0.0) ? 2 : 0;
+    put_digits_nb<D, XS>(row + (put ? col : K), put ? x : 0.0, Qd, it.bias, it.Bsplit, it.invBsplit, it.magic,
+                         it.shift, it.B, it.halfB);
+    const bool park = ends && rv;
+    const int rr = rv ? r : 0;
+    int8_t *slot = park ? row + (rr / SPR) * (kCT * XS) + (rr % SPR) * 8 : row + K;
+    *reinterpret_cast<double *>(slot) = x;
+}
+
+// One phase: the products of tile P (planes Xp -> accP) interleaved with the
+// finish of tile F (accF -> planes Xf), digit plane by digit plane: after the
+// MFMAs of plane j come the finish of output group j and a scheduling fence.
+template <int NRT, int NKB, int D, int NV, bool Z32, int J>
+__device__ __forceinline__ static void mfma5_phase_step(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
+                                                        v16i (&accP)[D], const v16i (&accF)[D],
+                                                        const uint32_t (&sl)[16], const TileState<NV> &tsF,
+                                                        const int16_t *cm, int8_t *rowF, const DevDigitItem &it,
+                                                        int &bad) {
+    constexpr int XS = NKB * 32 + 16;
+    if constexpr (J < D) {
+        v4i xb[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; kb++)
+            xb[kb] = *reinterpret_cast<const v4i *>(Xp + (J * kCT + c) * XS + kb * 32 + half * 16);
+#pragma unroll
+        for (int i = 0; i + J < D; i++)
+#pragma unroll
+            for (int kb = 0; kb < NKB; kb++)
+                accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], accP[i + J], 0, 0, 0);
+    }
+    if constexpr (J < slot_groups(NRT)) mfma5_finish_group<NRT, NKB, D, NV, Z32, J>(accF, sl, tsF, cm, rowF, it, bad);
+    if constexpr (J < D) {
+        constexpr int NM = (D - J) * NKB;
+#pragma unroll
+        for (int q = 0; q < NM; q++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then some VALU
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int JMAX = D > slot_groups(NRT) ? D : slot_groups(NRT);
+    if constexpr (J + 1 < JMAX)
+        mfma5_phase_step<NRT, NKB, D, NV, Z32, J + 1>(A, Xp, c, half, accP, accF, sl, tsF, cm, rowF, it, bad);
+}
+
+// After the barrier: the parked outputs of the chains that ended go out.
+template <int NRT, int NKB, int NV>
+__device__ __forceinline__ static void mfma5_flush(const DevFamily &fam, const TileState<NV> &ts, const int8_t *Xn,
+                                                   int c, int bin, int chain0, const DevDigitItem &it,
+                                                   uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf,
+                                                   int &bad) {
+    constexpr int K = NKB * 32;
+    constexpr int XS = K + 16;
+    constexpr int SPR = K / 8;
+    if (!(ts.act && !ts.more)) return;
+    const int s = fam.s;
+    const double qd = (double)it.q, invq = 1.0 / qd;
+    for (int r = bin; r < s; r += 2 * NRT) {
+        const double x = *reinterpret_cast<const double *>(Xn + c * XS + (r / SPR) * (kCT * XS) + (r % SPR) * 8);
+        if (x == 0.0) continue;
+        const uint64_t v = (uint64_t)mod_fp(x, qd, invq);
+        if (ts.vout >= 0) {
+            store[(size_t)ts.vout * s + r] = v;
+        } else if (ts.fin_row >= 0) {
+            const int f = fam.finmap[ts.fin_row + r];
+            if (f < 0) bad |= 4;
+            else hbuf[(size_t)(chain0 + c) * fam.F + f] = v;
+        }
+    }
+}
+
+// clear one set of digit planes (XB bytes) with NT threads, constant trip count
+template <int NT, int XB>
+__device__ __forceinline__ static void mfma5_zero(int8_t *X, int tid) {
+    constexpr int N16 = XB / 16;
+#pragma unroll
+    for (int q = 0; q < N16 / NT; q++) reinterpret_cast<v4i *>(X)[tid + q * NT] = v4i{0, 0, 0, 0};
+    if (N16 % NT != 0 && tid < N16 % NT) reinterpret_cast<v4i *>(X)[(N16 / NT) * NT + tid] = v4i{0, 0, 0, 0};
+}
+
+// Ask the scheduler to alternate the products of one tile with the finishing
+// arithmetic of the other: one MFMA, then a few VALU instructions, repeated.
+template <int NKB, int D>
+__device__ __forceinline__ static void mfma5_interleave() {
+    constexpr int NM = D * (D + 1) / 2 * NKB;
+#pragma unroll
+    for (int i = 0; i < NM; i++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);  // VALU
+    }
+}
+
+template <int NRT, int NKB, int D>
+constexpr size_t mfma5_lds_bytes() {
+    return (size_t)4 * D * kCT * (NKB * 32 + 16) + kTabCap * 2 + 512;
+}
+
+// One pair of tiles (tiles[0], tiles[1]: same item) on the LDS at lds.
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const DevDigitItem *__restrict__ items,
+                                  const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
+                                  const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
+                                  uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf, const uint32_t (&sl)[16],
+                                  int *__restrict__ err, int8_t *Xall, const int16_t *colmapL, const int8_t *dirsL) {
+    constexpr int K = NKB * 32;
+    constexpr int XS = K + 16;
+    constexpr int NT = 64 * NRT;
+    constexpr int XB = D * kCT * XS;
+    (void)K;
+    const DevTile tA = tp[0], tB = tp[1];
+    const DevDigitItem it = items[tA.item];
+    const int s = fam.s, F = fam.F;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 31, half = lane >> 5, bin = 2 * wave + half;
+    int8_t *XA = Xall, *XBp = Xall + 2 * XB;  // two plane sets per tile
+
+    v4i A[D][NKB];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int kb = 0; kb < NKB; kb++)
+            A[i][kb] = *reinterpret_cast<const v4i *>(it.apack + ((((size_t)wave * D + i) * NKB + kb) * 64 + lane) * 16);
+    for (int idx = tid; idx < 4 * XB / 16; idx += NT) reinterpret_cast<v4i *>(Xall)[idx] = v4i{0, 0, 0, 0};
+    for (int t = 0; t < 2; t++) {
+        const DevTile &tl = t ? tB : tA;
+        for (int idx = tid; idx < tl.count * F; idx += NT)
+            if (vx[tl.chain0 + idx / F].out < 0) hbuf[(size_t)tl.chain0 * F + idx] = 0;
+        for (int idx = tid; idx < tl.count * s; idx += NT) {
+            const int out = vx[tl.chain0 + idx / s].out;
+            if (out >= 0) store[(size_t)out * s + idx % s] = 0;
+        }
+    }
+    __syncthreads();
+    TileState<NV> sA, sB;
+    mfma5_init<NRT, NKB, D, NV>(fam, tA, it, cu, cg, cpole, vx, store, err, XA, colmapL, dirsL, sA);
+    mfma5_init<NRT, NKB, D, NV>(fam, tB, it, cu, cg, cpole, vx, store, err, XBp, colmapL, dirsL, sB);
+    __syncthreads();
+
+    int bad = 0, ca = 0, cb = 0;
+    v16i accA[D], accB[D];
+    mfma5_products<NKB, D>(A, XA, c, half, accA);
+    const int steps = max(tA.steps, tB.steps);
+    for (int step = 0; step < steps; step++) {
+        // phase 1: products of B || finish of A
+        mfma5_book<NV>(fam, dirsL, sA, bad);
+#pragma unroll
+        for (int k = 0; k < D; k++) accB[k] = v16i{0};
+        mfma5_phase_step<NRT, NKB, D, NV, Z32, 0>(A, XBp + cb * XB, c, half, accB, accA, sl, sA,
+                                                  colmapL + sA.dirn * s, XA + (ca ^ 1) * XB + c * XS, it, bad);
+        mfma5_zero<NT, XB>(XA + ca * XB, tid);
+        __syncthreads();
+        mfma5_flush<NRT, NKB, NV>(fam, sA, XA + (ca ^ 1) * XB, c, bin, tA.chain0, it, store, hbuf, bad);
+        mfma5_advance<NV>(sA);
+        ca ^= 1;
+        // phase 2: products of A (next step) || finish of B
+        mfma5_book<NV>(fam, dirsL, sB, bad);
+#pragma unroll
+        for (int k = 0; k < D; k++) accA[k] = v16i{0};
+        mfma5_phase_step<NRT, NKB, D, NV, Z32, 0>(A, XA + ca * XB, c, half, accA, accB, sl, sB,
+                                                  colmapL + sB.dirn * s, XBp + (cb ^ 1) * XB + c * XS, it, bad);
+        mfma5_zero<NT, XB>(XBp + cb * XB, tid);
+        __syncthreads();
+        mfma5_flush<NRT, NKB, NV>(fam, sB, XBp + (cb ^ 1) * XB, c, bin, tB.chain0, it, store, hbuf, bad);
+        mfma5_advance<NV>(sB);
+        cb ^= 1;
+    }
+    if (bad) atomicOr(err, bad);
+    __syncthreads();  // the planes are reused by the next pair
+}
+
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__global__ __launch_bounds__(64 * NRT) void k_reduce_mfma5(DevFamily fam, const DevDigitItem *__restrict__ items,
+                                                           const DevTile *__restrict__ tiles, int npairs,
+                                                           int *__restrict__ queue, const int16_t *__restrict__ cu,
+                                                           const int32_t *__restrict__ cg,
+                                                           const int32_t *__restrict__ cpole,
+                                                           const DevVec *__restrict__ vx,
+                                                           uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf,
+                                                           const uint32_t *__restrict__ slots, int *__restrict__ err) {
+    extern __shared__ __align__(16) unsigned char lds5[];
+    constexpr int XB = D * kCT * (NKB * 32 + 16);
+    int8_t *Xall = reinterpret_cast<int8_t *>(lds5);
+    int16_t *colmapL = reinterpret_cast<int16_t *>(lds5 + 4 * XB);
+    int8_t *dirsL = reinterpret_cast<int8_t *>(colmapL + kTabCap);
+    __shared__ int next;
+    uint32_t sl[16];
+    mfma4_prologue<NRT, NKB, D, NV, Z32>(fam, slots, sl, colmapL, dirsL);
+    if (!queue) {  // one pair per workgroup
+        mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * blockIdx.x, items, cu, cg, cpole, vx, store, hbuf, sl, err,
+                                         Xall, colmapL, dirsL);
+        return;
+    }
+    for (;;) {  // persistent: pairs drained through the counter
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int pi = next;
+        __syncthreads();
+        if (pi >= npairs) break;
+        mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * pi, items, cu, cg, cpole, vx, store, hbuf, sl, err, Xall,
+                                         colmapL, dirsL);
+    }
+}
+
+template <int R, int KB, int DD, bool ZZ>
+static hipError_t launch_one5(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int npairs,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
+                              hipStream_t stream) {
+    constexpr size_t lds = mfma5_lds_bytes<R, KB, DD>();
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_mfma5<R, KB, DD, 3, ZZ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int grid = npairs;
+    if (pgrid > 0) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = std::min(npairs, std::max(1, cus) * pgrid);
+    }
+    hipLaunchKernelGGL((k_reduce_mfma5<R, KB, DD, 3, ZZ>), dim3(grid), dim3(64 * R), lds, stream, fam, items, tiles,
+                       npairs, pgrid > 0 ? queue : nullptr, cu, cg, cpole, vx, store, hbuf, slots, err);
+    return hipGetLastError();
+}
+
+bool mfma5_supports(const DevFamily &fam, int D);
+
+// tiles: 2 * npairs entries, pair i = (tiles[2i], tiles[2i+1]) of one item
+hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int npairs,
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
+                               int pgrid, int *queue, hipStream_t stream);
+
 bool mfma_shape(const DevFamily &fam, int &nrt, int &nkb) {
     nrt = (fam.nsrc + 31) / 32;
     nkb = (fam.T + 31) / 32;
@@ -761,6 +1242,41 @@ hipError_t launch_reduce_mfma4(const DevFamily &fam, const DevDigitItem *items, 
     CRF_LAUNCH4(4, 3, 8)
     CRF_LAUNCH4(4, 3, 10)
 #undef CRF_LAUNCH4
+    return hipErrorInvalidValue;
+}
+
+bool mfma5_supports(const DevFamily &fam, int D) {
+    int nrt, nkb;
+    if (!mfma4_supports(fam, D)) return false;
+    mfma4_shape(fam, nrt, nkb);
+    // the parked outputs of an ending chain (s values of 8 bytes, nkb*4 per
+    // plane row) must fit in its D plane rows
+    if ((fam.s + nkb * 4 - 1) / (nkb * 4) > D) return false;
+    return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));
+}
+
+hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int npairs,
+                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
+                               int pgrid, int *queue, hipStream_t stream) {
+    if (npairs == 0) return hipSuccess;
+    int nrt, nkb;
+    if (!mfma5_supports(fam, D)) return hipErrorInvalidValue;
+    mfma4_shape(fam, nrt, nkb);
+#define CRF_LAUNCH5(R, KB, DD)                                                                                      \
+    if (nrt == R && nkb == KB && D == DD) {                                                                         \
+        if (z32)                                                                                                    \
+            return launch_one5<R, KB, DD, true>(fam, items, tiles, npairs, cu, cg, cpole, vx, store, hbuf, slots,   \
+                                                err, pgrid, queue, stream);                                         \
+        return launch_one5<R, KB, DD, false>(fam, items, tiles, npairs, cu, cg, cpole, vx, store, hbuf, slots, err, \
+                                             pgrid, queue, stream);                                                 \
+    }
+    CRF_LAUNCH5(2, 2, 3)
+    CRF_LAUNCH5(2, 2, 6)
+    CRF_LAUNCH5(4, 3, 5)
+    CRF_LAUNCH5(4, 3, 8)
+    CRF_LAUNCH5(4, 3, 10)
+#undef CRF_LAUNCH5
     return hipErrorInvalidValue;
 }
 

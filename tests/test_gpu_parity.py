@@ -18,14 +18,16 @@ from tests.gpu_common import assert_item_matches_oracle, run_batch, workload_ite
 pytestmark = pytest.mark.gpu
 
 
-ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU, C.ENGINE_MFMA_LDS]
+ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU, C.ENGINE_MFMA_LDS, C.ENGINE_MFMA_SINGLE]
 
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_quartic_curve_f7(engine):
     items = workload_items("quartic_curve_f7", [0])
     res = run_batch(3, 4, items, engine=engine)
-    assert res["stats"].engine == engine
+    # D = 3 digits at p = 7: too few plane rows to park 28 outputs, so the
+    # default engine runs the single-tile register-gather kernel
+    assert res["stats"].engine == (C.ENGINE_MFMA_SINGLE if engine == C.ENGINE_AUTO else engine)
     assert_item_matches_oracle(res, 0, 3, 4, *items[0])
 
 
