@@ -698,11 +698,12 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t stream) {
 //   phase 1: products of tile B (step t)   || finish of tile A (step t)
 //   phase 2: products of tile A (step t+1) || finish of tile B (step t)
 // The finish of a tile (weighted gather, exact recombination, digit split)
-// is branch-free: a digit that has nowhere to go is written to the pad
-// column of its plane row (never read by the products), and the outputs of a
-// chain that ends at this step are parked as 8-byte values in its own rows of
-// the next planes (which no later step of that chain reads), then written
-// out after the barrier.
+// is branch-free: the new digits come from a carry propagation over the
+// digit-position sums (no recombination), a digit that has nowhere to go is
+// written to the pad column of its plane row (never read by the products),
+// and the digits of a chain that ends at this step are parked at column r of
+// its own rows of the next planes (which no later step of that chain reads),
+// then turned into residues and written out after the barrier.
 // Branch-free forms of mod_fp and put_digits (the corrections are added as
 // multiples of the flag), so that a whole finishing block is one basic block.
 __device__ __forceinline__ double mod_fp_nb(double x, double Q, double invQ) {
@@ -892,7 +893,6 @@ __device__ __forceinline__ static void mfma5_finish_group(const v16i (&acc)[D], 
                                                           const DevDigitItem &it, int &bad) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
-    constexpr int SPR = K / 8;  // 8-byte parking slots per plane row
     constexpr int gs = slot_group(NRT, G);
     constexpr int j0 = [] {
         int t = 0;
@@ -924,28 +924,39 @@ __device__ __forceinline__ static void mfma5_finish_group(const v16i (&acc)[D], 
         }
     }
     const int r = (int)(wend >> 16);
-    constexpr int H = D / 2;
-    double lo = 0.0, hi = 0.0;
-#pragma unroll
-    for (int k = D - 1; k >= 0; k--) {
-        const double zk = Z32 ? (double)zi[k] : zd[k];
-        if (k >= H) hi = fma(hi, it.Bd, zk);
-        else lo = fma(lo, it.Bd, zk);
-    }
-    const double Qd = it.Qd;
-    double x = mod_fp_nb(lo, Qd, it.invQ);
-    x = fma(mod_fp_nb(hi, it.BHd, it.invBH), it.Bh, x);
-    x -= Qd * (double)(x >= Qd);
+    // balanced base-B digits of w'[r] = sum_k Z_k B^k mod Q' by carry
+    // propagation: t = Z_k + carry, carry = round(t / B), d_k = t - B carry
+    // (|d_k| <= (B-1)/2 since B is odd); the carry out of position D - 1 is a
+    // multiple of Q' and is dropped.  round() adds and subtracts 1.5 2^52; for
+    // |t| < 2^32 (Z32) its error (< 2^-23) cannot carry t / B across a
+    // half-integer (t / B lies at least 1 / (2B) from one), so it is exact;
+    // for wider sums a range test fixes the one-unit error it can make.
     const bool rv = r != 0xFFFF;
     const int col = cm[rv ? r : 0];
     const bool put = cont && rv && col >= 0;
-    bad |= (cont && rv && col < 0 && x != 0.0) ? 2 : 0;
-    put_digits_nb<D, XS>(row + (put ? col : K), put ? x : 0.0, Qd, it.bias, it.Bsplit, it.invBsplit, it.magic,
-                         it.shift, it.B, it.halfB);
     const bool park = ends && rv;
-    const int rr = rv ? r : 0;
-    int8_t *slot = park ? row + (rr / SPR) * (kCT * XS) + (rr % SPR) * 8 : row + K;
-    *reinterpret_cast<double *>(slot) = x;
+    int8_t *dst = row + (put ? col : (park ? r : K));  // parked digits sit at column r
+    const double Bd = it.Bd, invB = 1.0 / Bd, hB = (double)it.halfB;
+    constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
+    double carry = 0.0;
+    int nz = 0;  // balanced digits of 0 mod Q' are all 0
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const double t = (Z32 ? (double)zi[k] : zd[k]) + carry;
+        double q = fma(t, invB, kRound) - kRound;
+        double dk = fma(-q, Bd, t);
+        if (!Z32) {
+            const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
+            q += up1 - dn1;
+            dk += Bd * (dn1 - up1);
+        }
+        carry = q;
+        const int di = (int)dk;
+        nz |= di;
+        dst[k * kCT * XS] = (int8_t)di;
+    }
+    // an output with no column under the chosen direction must vanish
+    bad |= (cont && rv && col < 0 && nz != 0) ? 2 : 0;
 }
 
 // One phase: the products of tile P (planes Xp -> accP) interleaved with the
@@ -985,19 +996,20 @@ __device__ __forceinline__ static void mfma5_phase_step(const v4i (&A)[D][NKB], 
 }
 
 // After the barrier: the parked outputs of the chains that ended go out.
-template <int NRT, int NKB, int NV>
+template <int NRT, int NKB, int D, int NV>
 __device__ __forceinline__ static void mfma5_flush(const DevFamily &fam, const TileState<NV> &ts, const int8_t *Xn,
                                                    int c, int bin, int chain0, const DevDigitItem &it,
                                                    uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf,
                                                    int &bad) {
-    constexpr int K = NKB * 32;
-    constexpr int XS = K + 16;
-    constexpr int SPR = K / 8;
+    constexpr int XS = NKB * 32 + 16;
     if (!(ts.act && !ts.more)) return;
     const int s = fam.s;
-    const double qd = (double)it.q, invq = 1.0 / qd;
+    const double qd = (double)it.q, invq = 1.0 / qd, Bd = it.Bd, Qd = it.Qd;
     for (int r = bin; r < s; r += 2 * NRT) {
-        const double x = *reinterpret_cast<const double *>(Xn + c * XS + (r / SPR) * (kCT * XS) + (r % SPR) * 8);
+        // x = sum_k d_k B^k from the digits parked at column r (|x| < Q' / 2)
+        double x = 0.0;
+        for (int k = D - 1; k >= 0; k--) x = fma(x, Bd, (double)Xn[k * kCT * XS + c * XS + r]);
+        if (x < 0.0) x += Qd;
         if (x == 0.0) continue;
         const uint64_t v = (uint64_t)mod_fp(x, qd, invq);
         if (ts.vout >= 0) {
@@ -1090,7 +1102,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
                                                   colmapL + sA.dirn * s, XA + (ca ^ 1) * XB + c * XS, it, bad);
         mfma5_zero<NT, XB>(XA + ca * XB, tid);
         __syncthreads();
-        mfma5_flush<NRT, NKB, NV>(fam, sA, XA + (ca ^ 1) * XB, c, bin, tA.chain0, it, store, hbuf, bad);
+        mfma5_flush<NRT, NKB, D, NV>(fam, sA, XA + (ca ^ 1) * XB, c, bin, tA.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sA);
         ca ^= 1;
         // phase 2: products of A (next step) || finish of B
@@ -1101,7 +1113,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
                                                   colmapL + sB.dirn * s, XBp + (cb ^ 1) * XB + c * XS, it, bad);
         mfma5_zero<NT, XB>(XBp + cb * XB, tid);
         __syncthreads();
-        mfma5_flush<NRT, NKB, NV>(fam, sB, XBp + (cb ^ 1) * XB, c, bin, tB.chain0, it, store, hbuf, bad);
+        mfma5_flush<NRT, NKB, D, NV>(fam, sB, XBp + (cb ^ 1) * XB, c, bin, tB.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sB);
         cb ^= 1;
     }
@@ -1249,9 +1261,8 @@ bool mfma5_supports(const DevFamily &fam, int D) {
     int nrt, nkb;
     if (!mfma4_supports(fam, D)) return false;
     mfma4_shape(fam, nrt, nkb);
-    // the parked outputs of an ending chain (s values of 8 bytes, nkb*4 per
-    // plane row) must fit in its D plane rows
-    if ((fam.s + nkb * 4 - 1) / (nkb * 4) > D) return false;
+    // the digits of an ending chain are parked at columns r < s of its rows
+    if (fam.s > nkb * 32) return false;
     return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));
 }
 

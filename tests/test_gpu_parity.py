@@ -25,9 +25,7 @@ ENGINES = [C.ENGINE_AUTO, C.ENGINE_VALU, C.ENGINE_MFMA_LDS, C.ENGINE_MFMA_SINGLE
 def test_quartic_curve_f7(engine):
     items = workload_items("quartic_curve_f7", [0])
     res = run_batch(3, 4, items, engine=engine)
-    # D = 3 digits at p = 7: too few plane rows to park 28 outputs, so the
-    # default engine runs the single-tile register-gather kernel
-    assert res["stats"].engine == (C.ENGINE_MFMA_SINGLE if engine == C.ENGINE_AUTO else engine)
+    assert res["stats"].engine == engine
     assert_item_matches_oracle(res, 0, 3, 4, *items[0])
 
 
