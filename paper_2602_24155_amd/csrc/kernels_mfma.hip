@@ -883,116 +883,181 @@ __device__ __forceinline__ static void mfma5_products(const v4i (&A)[D][NKB], co
     }
 }
 
-// Branch-free finish of output group g of one tile's step: digits of
-// continuing chains go to their columns of the next planes Xn, the 8-byte
-// outputs of ending chains to their own rows of Xn (slot r: plane r / (K/8),
-// column 8 (r mod (K/8))), everything else to the pad column K.
-template <int NRT, int NKB, int D, int NV, bool Z32, int G>
-__device__ __forceinline__ static void mfma5_finish_group(const v16i (&acc)[D], const uint32_t (&sl)[16],
-                                                          const TileState<NV> &ts, const int16_t *cm, int8_t *row,
-                                                          const DevDigitItem &it, int &bad) {
+// The finish of one output group of a tile's step is split into D pieces,
+// one per digit position k: z_k = sum over the group's slots of weight *
+// product sum, then one carry step.  Digits of continuing chains go to their
+// columns of the next planes, those of a chain that ends at this step are
+// parked at column r of its own rows there, everything else goes to the pad
+// column K.  The state between the pieces of a group is a FinState.
+struct FinState {
+    int wt[3];
+    double carry;
+    int nz;          // OR of the digits: the balanced digits of 0 mod Q' are all 0
+    int8_t *dst;
+    bool chk;        // continuing chain whose output has no column under its direction
+};
+
+constexpr int slot_first(int nrt, int g) {  // first slot of output group g
+    int t = 0;
+    for (int q = 0; q < g; q++) t += slot_group(nrt, q);
+    return t;
+}
+
+template <int NRT, int NKB, int D, int NV, bool Z32, int P>
+__device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const uint32_t (&sl)[16],
+                                                   const TileState<NV> &ts, const int (&cols)[9], int8_t *row,
+                                                   const DevDigitItem &it, FinState &fs, int &bad) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
+    constexpr int G = P / D, k = P % D;
     constexpr int gs = slot_group(NRT, G);
-    constexpr int j0 = [] {
-        int t = 0;
-        for (int q = 0; q < G; q++) t += slot_group(NRT, q);
-        return t;
-    }();
-    const bool cont = ts.act && ts.more, ends = ts.act && !ts.more;
-    int zi[D];
-    double zd[D];
+    constexpr int j0 = slot_first(NRT, G);
+    if constexpr (k == 0) {
+        const bool cont = ts.act && ts.more, ends = ts.act && !ts.more;
 #pragma unroll
-    for (int k = 0; k < D; k++) {
-        zi[k] = 0;
-        zd[k] = 0.0;
-    }
-    uint32_t wend = 0;
-#pragma unroll
-    for (int m = 0; m < gs; m++) {
-        const int j = j0 + m;
-        const uint32_t w = sl[j];
-        wend = w;
-        const int iv = slot_var(NRT, G) < 0 ? m : slot_var(NRT, G);
-        const int wt = ts.up[iv] + (int)((w >> 5) & 2047u);
-        if (Z32) {
-#pragma unroll
-            for (int k = 0; k < D; k++) zi[k] += __mul24(wt, acc[k][j]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < D; k++) zd[k] = fma((double)wt, (double)acc[k][j], zd[k]);
+        for (int m = 0; m < gs; m++) {
+            const int iv = slot_var(NRT, G) < 0 ? m : slot_var(NRT, G);
+            fs.wt[m] = ts.up[iv] + (int)((sl[j0 + m] >> 5) & 2047u);
         }
+        const int r = (int)(sl[j0 + gs - 1] >> 16);
+        const bool rv = r != 0xFFFF;
+        const int col = cols[G];
+        const bool put = cont && rv && col >= 0;
+        const bool park = ends && rv;
+        fs.dst = row + (put ? col : (park ? r : K));
+        fs.carry = 0.0;
+        fs.nz = 0;
+        fs.chk = cont && rv && col < 0;
     }
-    const int r = (int)(wend >> 16);
-    // balanced base-B digits of w'[r] = sum_k Z_k B^k mod Q' by carry
-    // propagation: t = Z_k + carry, carry = round(t / B), d_k = t - B carry
-    // (|d_k| <= (B-1)/2 since B is odd); the carry out of position D - 1 is a
-    // multiple of Q' and is dropped.  round() adds and subtracts 1.5 2^52; for
-    // |t| < 2^32 (Z32) its error (< 2^-23) cannot carry t / B across a
-    // half-integer (t / B lies at least 1 / (2B) from one), so it is exact;
-    // for wider sums a range test fixes the one-unit error it can make.
-    const bool rv = r != 0xFFFF;
-    const int col = cm[rv ? r : 0];
-    const bool put = cont && rv && col >= 0;
-    const bool park = ends && rv;
-    int8_t *dst = row + (put ? col : (park ? r : K));  // parked digits sit at column r
-    const double Bd = it.Bd, invB = 1.0 / Bd, hB = (double)it.halfB;
+    // carry step at position k: t = z_k + carry, carry = round(t / B),
+    // d_k = t - B carry (|d_k| <= (B-1)/2 since B is odd); the carry out of
+    // position D - 1 is a multiple of Q' and is dropped.  round() adds and
+    // subtracts 1.5 2^52; for |t| < 2^32 (Z32) its error (< 2^-23) cannot
+    // carry t / B across a half-integer (t / B lies at least 1 / (2B) from
+    // one), so it is exact; for wider sums a range test fixes the one-unit
+    // error it can make.
+    double t;
+    if constexpr (Z32) {
+        int z = 0;
+#pragma unroll
+        for (int m = 0; m < gs; m++) z += __mul24(fs.wt[m], acc[k][j0 + m]);
+        t = (double)z + fs.carry;
+    } else {
+        double z = 0.0;
+#pragma unroll
+        for (int m = 0; m < gs; m++) z = fma((double)fs.wt[m], (double)acc[k][j0 + m], z);
+        t = z + fs.carry;
+    }
+    const double Bd = it.Bd, invB = 1.0 / Bd;
     constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
-    double carry = 0.0;
-    int nz = 0;  // balanced digits of 0 mod Q' are all 0
-#pragma unroll
-    for (int k = 0; k < D; k++) {
-        const double t = (Z32 ? (double)zi[k] : zd[k]) + carry;
-        double q = fma(t, invB, kRound) - kRound;
-        double dk = fma(-q, Bd, t);
-        if (!Z32) {
-            const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
-            q += up1 - dn1;
-            dk += Bd * (dn1 - up1);
-        }
-        carry = q;
-        const int di = (int)dk;
-        nz |= di;
-        dst[k * kCT * XS] = (int8_t)di;
+    double q = fma(t, invB, kRound) - kRound;
+    double dk = fma(-q, Bd, t);
+    if constexpr (!Z32) {
+        const double hB = (double)it.halfB;
+        const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
+        q += up1 - dn1;
+        dk += Bd * (dn1 - up1);
     }
-    // an output with no column under the chosen direction must vanish
-    bad |= (cont && rv && col < 0 && nz != 0) ? 2 : 0;
+    fs.carry = q;
+    const int di = (int)dk;
+    fs.nz |= di;
+    fs.dst[k * kCT * XS] = (int8_t)di;
+    if constexpr (k == D - 1) bad |= (fs.chk && fs.nz != 0) ? 2 : 0;
+}
+
+template <int NRT, int NKB, int D, int NV, bool Z32, int P, int P1>
+__device__ __forceinline__ static void mfma5_pieces(const v16i (&acc)[D], const uint32_t (&sl)[16],
+                                                    const TileState<NV> &ts, const int (&cols)[9], int8_t *row,
+                                                    const DevDigitItem &it, FinState &fs, int &bad) {
+    if constexpr (P < P1) {
+        mfma5_piece<NRT, NKB, D, NV, Z32, P>(acc, sl, ts, cols, row, it, fs, bad);
+        mfma5_pieces<NRT, NKB, D, NV, Z32, P + 1, P1>(acc, sl, ts, cols, row, it, fs, bad);
+    }
+}
+
+// The products of a phase as a list of units, one MFMA each: plane J
+// (products with digit J of the chains' vectors) holds the units (kb, i),
+// kb major, so consecutive MFMAs feed different accumulators.
+template <int D, int NKB>
+struct UnitMap {
+    static constexpr int count = D * (D + 1) / 2 * NKB;
+    static constexpr int plane(int u) {
+        int J = 0;
+        while (u >= (D - J) * NKB) u -= (D - J) * NKB, J++;
+        return J;
+    }
+    static constexpr int first(int J) {  // first unit of plane J
+        int t = 0;
+        for (int q = 0; q < J; q++) t += (D - q) * NKB;
+        return t;
+    }
+};
+
+// One unit of a phase: the MFMA of tile P's unit U, the finishing pieces of
+// tile F and the plane clearing stores that fall on it, then a scheduling
+// fence, so that each MFMA runs in the shadow of independent vector work.
+// The operands of plane J + 1 are read from LDS when plane J starts.
+template <int NRT, int NKB, int D, int NV, bool Z32, int U>
+__device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
+                                                  v4i (&xb)[2][NKB], v16i (&accP)[D], const v16i (&accF)[D],
+                                                  const uint32_t (&sl)[16], const TileState<NV> &tsF,
+                                                  const int (&cols)[9], int8_t *rowF, const DevDigitItem &it,
+                                                  FinState &fs, v4i *Xz, int tid, int &bad) {
+    using UM = UnitMap<D, NKB>;
+    constexpr int NU = UM::count;
+    if constexpr (U < NU) {
+        constexpr int XS = NKB * 32 + 16;
+        constexpr int J = UM::plane(U);
+        constexpr int w = U - UM::first(J);
+        constexpr int kb = w / (D - J), i = w % (D - J);
+        if constexpr (w == 0 && J + 1 < D) {
+#pragma unroll
+            for (int b = 0; b < NKB; b++)
+                xb[(J + 1) & 1][b] =
+                    *reinterpret_cast<const v4i *>(Xp + ((J + 1) * kCT + c) * XS + b * 32 + half * 16);
+        }
+        accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[J & 1][kb], accP[i + J], 0, 0, 0);
+        constexpr int NP = slot_groups(NRT) * D;
+        mfma5_pieces<NRT, NKB, D, NV, Z32, U * NP / NU, (U + 1) * NP / NU>(accF, sl, tsF, cols, rowF, it, fs, bad);
+        // plane clearing: NZ 16-byte stores per thread, spread over the phase
+        constexpr int NT = 64 * NRT;
+        constexpr int N16 = D * kCT * XS / 16;
+        constexpr int NZ = (N16 + NT - 1) / NT;
+        static_assert(NU >= NZ, "clearing stores per phase");
+        if constexpr (U % (NU / NZ) == 0 && U / (NU / NZ) < NZ) {
+            constexpr int zq = U / (NU / NZ);
+            if (zq * NT + tid < N16) Xz[zq * NT + tid] = v4i{0, 0, 0, 0};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mfma5_unit<NRT, NKB, D, NV, Z32, U + 1>(A, Xp, c, half, xb, accP, accF, sl, tsF, cols, rowF, it, fs, Xz, tid,
+                                                bad);
+    }
 }
 
 // One phase: the products of tile P (planes Xp -> accP) interleaved with the
-// finish of tile F (accF -> planes Xf), digit plane by digit plane: after the
-// MFMAs of plane j come the finish of output group j and a scheduling fence.
-template <int NRT, int NKB, int D, int NV, bool Z32, int J>
-__device__ __forceinline__ static void mfma5_phase_step(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
-                                                        v16i (&accP)[D], const v16i (&accF)[D],
-                                                        const uint32_t (&sl)[16], const TileState<NV> &tsF,
-                                                        const int16_t *cm, int8_t *rowF, const DevDigitItem &it,
-                                                        int &bad) {
+// finish of tile F (accF -> planes rowF) and the clearing of the planes Xz.
+template <int NRT, int NKB, int D, int NV, bool Z32>
+__device__ __forceinline__ static void mfma5_phase(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
+                                                   v16i (&accP)[D], const v16i (&accF)[D], const uint32_t (&sl)[16],
+                                                   const TileState<NV> &tsF, const int16_t *cm, int8_t *rowF,
+                                                   const DevDigitItem &it, int8_t *Xz, int tid, int &bad) {
     constexpr int XS = NKB * 32 + 16;
-    if constexpr (J < D) {
-        v4i xb[NKB];
+    constexpr int G = slot_groups(NRT);
+    static_assert(G <= 9, "slot groups");
+    int cols[9];
 #pragma unroll
-        for (int kb = 0; kb < NKB; kb++)
-            xb[kb] = *reinterpret_cast<const v4i *>(Xp + (J * kCT + c) * XS + kb * 32 + half * 16);
-#pragma unroll
-        for (int i = 0; i + J < D; i++)
-#pragma unroll
-            for (int kb = 0; kb < NKB; kb++)
-                accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], accP[i + J], 0, 0, 0);
+    for (int g = 0; g < G; g++) {
+        const int r = (int)(sl[slot_first(NRT, g) + slot_group(NRT, g) - 1] >> 16);
+        cols[g] = cm[r != 0xFFFF ? r : 0];
     }
-    if constexpr (J < slot_groups(NRT)) mfma5_finish_group<NRT, NKB, D, NV, Z32, J>(accF, sl, tsF, cm, rowF, it, bad);
-    if constexpr (J < D) {
-        constexpr int NM = (D - J) * NKB;
+    v4i xb[2][NKB];
 #pragma unroll
-        for (int q = 0; q < NM; q++) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then some VALU
-        }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    constexpr int JMAX = D > slot_groups(NRT) ? D : slot_groups(NRT);
-    if constexpr (J + 1 < JMAX)
-        mfma5_phase_step<NRT, NKB, D, NV, Z32, J + 1>(A, Xp, c, half, accP, accF, sl, tsF, cm, rowF, it, bad);
+    for (int b = 0; b < NKB; b++) xb[0][b] = *reinterpret_cast<const v4i *>(Xp + c * XS + b * 32 + half * 16);
+#pragma unroll
+    for (int k = 0; k < D; k++) accP[k] = v16i{0};
+    FinState fs;
+    mfma5_unit<NRT, NKB, D, NV, Z32, 0>(A, Xp, c, half, xb, accP, accF, sl, tsF, cols, rowF, it, fs,
+                                        reinterpret_cast<v4i *>(Xz), tid, bad);
 }
 
 // After the barrier: the parked outputs of the chains that ended go out.
@@ -1019,27 +1084,6 @@ __device__ __forceinline__ static void mfma5_flush(const DevFamily &fam, const T
             if (f < 0) bad |= 4;
             else hbuf[(size_t)(chain0 + c) * fam.F + f] = v;
         }
-    }
-}
-
-// clear one set of digit planes (XB bytes) with NT threads, constant trip count
-template <int NT, int XB>
-__device__ __forceinline__ static void mfma5_zero(int8_t *X, int tid) {
-    constexpr int N16 = XB / 16;
-#pragma unroll
-    for (int q = 0; q < N16 / NT; q++) reinterpret_cast<v4i *>(X)[tid + q * NT] = v4i{0, 0, 0, 0};
-    if (N16 % NT != 0 && tid < N16 % NT) reinterpret_cast<v4i *>(X)[(N16 / NT) * NT + tid] = v4i{0, 0, 0, 0};
-}
-
-// Ask the scheduler to alternate the products of one tile with the finishing
-// arithmetic of the other: one MFMA, then a few VALU instructions, repeated.
-template <int NKB, int D>
-__device__ __forceinline__ static void mfma5_interleave() {
-    constexpr int NM = D * (D + 1) / 2 * NKB;
-#pragma unroll
-    for (int i = 0; i < NM; i++) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);  // VALU
     }
 }
 
@@ -1096,22 +1140,16 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     for (int step = 0; step < steps; step++) {
         // phase 1: products of B || finish of A
         mfma5_book<NV>(fam, dirsL, sA, bad);
-#pragma unroll
-        for (int k = 0; k < D; k++) accB[k] = v16i{0};
-        mfma5_phase_step<NRT, NKB, D, NV, Z32, 0>(A, XBp + cb * XB, c, half, accB, accA, sl, sA,
-                                                  colmapL + sA.dirn * s, XA + (ca ^ 1) * XB + c * XS, it, bad);
-        mfma5_zero<NT, XB>(XA + ca * XB, tid);
+        mfma5_phase<NRT, NKB, D, NV, Z32>(A, XBp + cb * XB, c, half, accB, accA, sl, sA, colmapL + sA.dirn * s,
+                                          XA + (ca ^ 1) * XB + c * XS, it, XA + ca * XB, tid, bad);
         __syncthreads();
         mfma5_flush<NRT, NKB, D, NV>(fam, sA, XA + (ca ^ 1) * XB, c, bin, tA.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sA);
         ca ^= 1;
         // phase 2: products of A (next step) || finish of B
         mfma5_book<NV>(fam, dirsL, sB, bad);
-#pragma unroll
-        for (int k = 0; k < D; k++) accA[k] = v16i{0};
-        mfma5_phase_step<NRT, NKB, D, NV, Z32, 0>(A, XA + ca * XB, c, half, accA, accB, sl, sB,
-                                                  colmapL + sB.dirn * s, XBp + (cb ^ 1) * XB + c * XS, it, bad);
-        mfma5_zero<NT, XB>(XBp + cb * XB, tid);
+        mfma5_phase<NRT, NKB, D, NV, Z32>(A, XA + ca * XB, c, half, accA, accB, sl, sB, colmapL + sB.dirn * s,
+                                          XBp + (cb ^ 1) * XB + c * XS, it, XBp + cb * XB, tid, bad);
         __syncthreads();
         mfma5_flush<NRT, NKB, D, NV>(fam, sB, XBp + (cb ^ 1) * XB, c, bin, tB.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sB);
