@@ -354,6 +354,77 @@ __device__ __forceinline__ static void choose_chunk_reg(const DevFamily &fam, co
     }
 }
 
+// floor(u / v) for 0 <= u < 2^20 and 1 <= v <= 64: fp32 reciprocal estimate
+// (off by at most one) and an exact integer correction
+__device__ __forceinline__ static int div_small(int u, int v) {
+    int q = (int)((float)u * __frcp_rn((float)v));
+    q += (q + 1) * v <= u ? 1 : 0;
+    q -= q * v > u ? 1 : 0;
+    return q;
+}
+
+// Lookup tables of the pair kernel, built once per workgroup in LDS (3
+// variables): dirIdx[v0 + (d+1) v1] = index of the direction (v0, v1,
+// d - v0 - v1) in the family's list (-1 if absent); finIdx[u0 + 3 u1 + 9 u2]
+// = index of the final exponent (u0, u1, u2) (-1 if absent; final exponents
+// have |U| = |S| - 1 <= 2).
+constexpr int kDirLut = 512;
+constexpr int kFinLut = 32;
+
+__device__ static void build_luts3(const DevFamily &fam, int8_t *dirIdxL, int8_t *finIdxL, int tid, int nt) {
+    const int d1 = fam.d + 1;
+    for (int key = tid; key < d1 * d1; key += nt) {
+        const int v0 = key % d1, v1 = key / d1, v2 = fam.d - v0 - v1;
+        int t = -1;
+        for (int a = 0; a < fam.ndir && t < 0 && v2 >= 0; a++)
+            if (fam.dirs[a * 3] == v0 && fam.dirs[a * 3 + 1] == v1 && fam.dirs[a * 3 + 2] == v2) t = a;
+        dirIdxL[key] = (int8_t)t;
+    }
+    for (int key = tid; key < 27; key += nt) {
+        const int u0 = key % 3, u1 = (key / 3) % 3, u2 = key / 9;
+        int t = -1;
+        for (int a = 0; a < fam.nfinU && t < 0; a++)
+            if (fam.finU[a * 3] == u0 && fam.finU[a * 3 + 1] == u1 && fam.finU[a * 3 + 2] == u2) t = a;
+        finIdxL[key] = (int8_t)t;
+    }
+}
+
+// choose_chunk_reg for 3 variables with the direction found through dirIdx
+__device__ __forceinline__ static void choose_chunk_lut3(const DevFamily &fam, const int8_t *dirIdxL, const int *U,
+                                                         int poles_left, int *v, int &dir, int &k) {
+    int left = fam.d;
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[i] = 0;
+#pragma unroll
+    for (int sI = 0; sI < 3; sI++)
+        if (left > 0 && ((fam.smask >> sI) & 1u) && U[sI] != 0) {
+            v[sI] = 1;
+            left--;
+        }
+    for (int guard = 0; guard < 64 && left > 0; guard++) {
+        bool moved = false;
+#pragma unroll
+        for (int m = 0; m < 3; m++)
+            if (left > 0 && v[m] < U[m]) {
+                v[m]++;
+                left--;
+                moved = true;
+            }
+        if (!moved) break;
+    }
+    k = poles_left;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+        if (v[i]) k = min(k, div_small(U[i], v[i]));
+    dir = left == 0 ? dirIdxL[v[0] + (fam.d + 1) * v[1]] : -1;
+}
+
+// final-exponent index of U (3 variables), -1 if U is not one
+__device__ __forceinline__ static int fin_index3(const int8_t *finIdxL, const int *U) {
+    const bool ok = (unsigned)U[0] < 3u && (unsigned)U[1] < 3u && (unsigned)U[2] < 3u;
+    return ok ? finIdxL[U[0] + 3 * U[1] + 9 * U[2]] : -1;
+}
+
 // Balanced base-B digits of x (0 <= x < Q') written to the D digit planes at xp
 // (plane stride kCT * XS bytes).  x + bias is cut at B^DS so that both halves
 // stay below 2^24 for the 32-bit magic division by B.
@@ -753,7 +824,9 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
                                   const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                                   const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
                                   uint64_t *__restrict__ store, int *__restrict__ err, int8_t *X,
-                                  const int16_t *colmapL, const int8_t *dirsL, TileState<NV> &ts) {
+                                  const int16_t *colmapL, const int8_t *dirsL, const int8_t *dirIdxL,
+                                  TileState<NV> &ts) {
+    static_assert(NV == 3, "lookup tables are built for 3 variables");
     constexpr int XS = NKB * 32 + 16;
     const int s = fam.s, n = fam.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -780,7 +853,7 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
 #pragma unroll
         for (int i = 0; i < NV; i++) ts.V[i] = dirsL[d0 * NV + i];
     } else {
-        choose_chunk_reg<NV>(fam, dirsL, ts.U, ts.pole - ts.pend, ts.V, d0, k0);
+        choose_chunk_lut3(fam, dirIdxL, ts.U, ts.pole - ts.pend, ts.V, d0, k0);
     }
     if (d0 < 0 || k0 < 1) {
         if (wave == 0 && half == 0) atomicOr(err, 1);
@@ -813,8 +886,8 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
 
 // exponent after the step, next direction and chunk, final-exponent row
 template <int NV>
-__device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const int8_t *dirsL, TileState<NV> &ts,
-                                                  int &bad) {
+__device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const int8_t *dirIdxL,
+                                                  const int8_t *finIdxL, TileState<NV> &ts, int &bad) {
     ts.act = ts.pole > ts.pend;
     ts.dirn = ts.dir;
     ts.kleftn = ts.kleft - 1;
@@ -826,7 +899,7 @@ __device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const in
     ts.more = ts.act && ts.pole - 1 > ts.pend;
     if (ts.more && ts.kleftn == 0) {
         int d0, k0;
-        choose_chunk_reg<NV>(fam, dirsL, ts.up, ts.pole - 1 - ts.pend, ts.Vn, d0, k0);
+        choose_chunk_lut3(fam, dirIdxL, ts.up, ts.pole - 1 - ts.pend, ts.Vn, d0, k0);
         if (d0 < 0 || k0 < 1) {
             bad |= 1;
             d0 = 0;
@@ -837,13 +910,7 @@ __device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const in
     }
     ts.fin_row = -1;
     if (ts.act && !ts.more && ts.vout < 0) {
-        int Ui = -1;
-        for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
-            bool eq = true;
-#pragma unroll
-            for (int i = 0; i < NV; i++) eq = eq && (fam.finU[a * NV + i] == ts.up[i]);
-            if (eq) Ui = a;
-        }
+        const int Ui = fin_index3(finIdxL, ts.up);
         if (Ui < 0) bad |= 4;
         else ts.fin_row = Ui * fam.s;
     }
@@ -1089,7 +1156,7 @@ __device__ __forceinline__ static void mfma5_flush(const DevFamily &fam, const T
 
 template <int NRT, int NKB, int D>
 constexpr size_t mfma5_lds_bytes() {
-    return (size_t)4 * D * kCT * (NKB * 32 + 16) + kTabCap * 2 + 512;
+    return (size_t)4 * D * kCT * (NKB * 32 + 16) + kTabCap * 2 + 512 + kDirLut + kFinLut;
 }
 
 // One pair of tiles (tiles[0], tiles[1]: same item) on the LDS at lds.
@@ -1098,7 +1165,8 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
                                   const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                                   const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
                                   uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf, const uint32_t (&sl)[16],
-                                  int *__restrict__ err, int8_t *Xall, const int16_t *colmapL, const int8_t *dirsL) {
+                                  int *__restrict__ err, int8_t *Xall, const int16_t *colmapL, const int8_t *dirsL,
+                                  const int8_t *dirIdxL, const int8_t *finIdxL) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
     constexpr int NT = 64 * NRT;
@@ -1129,8 +1197,8 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     }
     __syncthreads();
     TileState<NV> sA, sB;
-    mfma5_init<NRT, NKB, D, NV>(fam, tA, it, cu, cg, cpole, vx, store, err, XA, colmapL, dirsL, sA);
-    mfma5_init<NRT, NKB, D, NV>(fam, tB, it, cu, cg, cpole, vx, store, err, XBp, colmapL, dirsL, sB);
+    mfma5_init<NRT, NKB, D, NV>(fam, tA, it, cu, cg, cpole, vx, store, err, XA, colmapL, dirsL, dirIdxL, sA);
+    mfma5_init<NRT, NKB, D, NV>(fam, tB, it, cu, cg, cpole, vx, store, err, XBp, colmapL, dirsL, dirIdxL, sB);
     __syncthreads();
 
     int bad = 0, ca = 0, cb = 0;
@@ -1139,7 +1207,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     const int steps = max(tA.steps, tB.steps);
     for (int step = 0; step < steps; step++) {
         // phase 1: products of B || finish of A
-        mfma5_book<NV>(fam, dirsL, sA, bad);
+        mfma5_book<NV>(fam, dirIdxL, finIdxL, sA, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XBp + cb * XB, c, half, accB, accA, sl, sA, colmapL + sA.dirn * s,
                                           XA + (ca ^ 1) * XB + c * XS, it, XA + ca * XB, tid, bad);
         __syncthreads();
@@ -1147,7 +1215,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
         mfma5_advance<NV>(sA);
         ca ^= 1;
         // phase 2: products of A (next step) || finish of B
-        mfma5_book<NV>(fam, dirsL, sB, bad);
+        mfma5_book<NV>(fam, dirIdxL, finIdxL, sB, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XA + ca * XB, c, half, accA, accB, sl, sB, colmapL + sB.dirn * s,
                                           XBp + (cb ^ 1) * XB + c * XS, it, XBp + cb * XB, tid, bad);
         __syncthreads();
@@ -1173,12 +1241,15 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma5(DevFamily fam, const 
     int8_t *Xall = reinterpret_cast<int8_t *>(lds5);
     int16_t *colmapL = reinterpret_cast<int16_t *>(lds5 + 4 * XB);
     int8_t *dirsL = reinterpret_cast<int8_t *>(colmapL + kTabCap);
+    int8_t *dirIdxL = dirsL + 512;
+    int8_t *finIdxL = dirIdxL + kDirLut;
     __shared__ int next;
     uint32_t sl[16];
     mfma4_prologue<NRT, NKB, D, NV, Z32>(fam, slots, sl, colmapL, dirsL);
+    build_luts3(fam, dirIdxL, finIdxL, threadIdx.x, 64 * NRT);  // published by the pair's first barrier
     if (!queue) {  // one pair per workgroup
         mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * blockIdx.x, items, cu, cg, cpole, vx, store, hbuf, sl, err,
-                                         Xall, colmapL, dirsL);
+                                         Xall, colmapL, dirsL, dirIdxL, finIdxL);
         return;
     }
     for (;;) {  // persistent: pairs drained through the counter
@@ -1188,7 +1259,7 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma5(DevFamily fam, const 
         __syncthreads();
         if (pi >= npairs) break;
         mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * pi, items, cu, cg, cpole, vx, store, hbuf, sl, err, Xall,
-                                         colmapL, dirsL);
+                                         colmapL, dirsL, dirIdxL, finIdxL);
     }
 }
 
@@ -1301,6 +1372,8 @@ bool mfma5_supports(const DevFamily &fam, int D) {
     mfma4_shape(fam, nrt, nkb);
     // the digits of an ending chain are parked at columns r < s of its rows
     if (fam.s > nkb * 32) return false;
+    // direction and final-exponent lookup tables (3 variables, |U| = 2 at the end)
+    if ((fam.d + 1) * (fam.d + 1) > kDirLut || fam.ndir > 127 || fam.nfinU > 127) return false;
     return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));
 }
 
