@@ -105,6 +105,7 @@ def main():
               "(the hypersurfaces of a batch are independent; see DESIGN.md for how it would shard)",
               file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     from paper_2602_24155_amd import crfrob as C
     from paper_2602_24155_amd import workload
@@ -115,8 +116,8 @@ def main():
     w = workload.WORKLOADS[args.workload]
     fam = C.family(w.nvars, w.degree, w.s_mask)
     items = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(fam, p, c)) for j in range(w.count)]
-    primes = [p for p, _ in items]
-    coeffs = [c for _, c in items]
+    primes = np.asarray([p for p, _ in items], dtype=np.int32)
+    coeffs = np.asarray([c for _, c in items], dtype=np.uint32)
     pol_names = ["depth-first", "p-chunk", "var-by-var", "learned"]
     launch_names = ["grid", "persistent", "graph"]
     tuning = None
@@ -151,7 +152,7 @@ def main():
     # algorithmic work of one step: column_steps products s x s . s mod p^M,
     # priced as int8 MFMA ops with L balanced base-256 digits per residue
     work = 0
-    for p in sorted(set(primes)):
+    for p in sorted(set(int(q) for q in primes)):
         _r, _N, M = C.cr_precision(fam, p)
         L = limbs_for(p ** M)
         work_p = 2 * s * s * L * L
@@ -174,7 +175,7 @@ def main():
         "dtype": "u64 residues mod p^M (int8-limb / int32 exact products)",
         "data": "synthetic: seeded random dense smooth curves, coefficients uniform in F_p",
         "config": {"workload": args.workload, "count": len(items), "nvars": w.nvars, "degree": w.degree,
-                   "primes": sorted(set(primes)), "policy": pol_names[fam.policy],
+                   "primes": sorted(set(int(q) for q in primes)), "policy": pol_names[fam.policy],
                    "launch": launch_names[fam.launch], "autotune_ms_per_call": tuning,
                    "start_blocks": st.start_blocks, "column_steps_per_step": st.column_steps,
                    "vectors_per_step": st.vectors, "merged_terms_per_step": st.merged_terms},

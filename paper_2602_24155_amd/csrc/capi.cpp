@@ -115,7 +115,8 @@ struct FamilyEntry {
 };
 
 std::mutex g_mutex;
-Arena g_arenas[2];  // alternate between consecutive sub-batches of a call
+constexpr int kArenas = 2;
+Arena g_arenas[kArenas];  // sub-batch k of a call uses arena k mod kArenas
 std::map<std::string, hipGraphExec_t> g_graphs;  // captured reduction launches by launch signature
 hipStream_t g_capture = nullptr;                 // private stream used for graph capture
 hipStream_t g_aux = nullptr;                     // upload and psi of the next sub-batch
@@ -177,6 +178,7 @@ class Pool {
         static Pool p;
         return p;
     }
+    int width() const { return (int)workers_.size() + 1; }
     void run(int count, const std::function<void(int)> &fn) {
         if (count <= 0) return;
         if (in_task || workers_.empty() || count == 1) {
@@ -391,6 +393,7 @@ struct BatchCtx {
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
+    hipEvent_t gate = nullptr;  // start of the last launched sub-batch's reductions (main stream)
     const int32_t *primes = nullptr;
     const uint32_t *coeffs = nullptr;
     Outputs out{};
@@ -832,12 +835,16 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     if (ctx.device_psi) {
         // upload, psi of every item and (MFMA path) its digits in the kernel's
         // fragment order on the auxiliary stream: this overlaps the reduction of
-        // the previous sub-batch (whose arena is the other one); the main stream
+        // the previous sub-batches (whose arenas are the other ones); the main stream
         // waits for it before the reductions
         if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
         (void)hipEventCreate(&sb.ep);
         (void)hipEventCreate(&sb.epe);
         if (he == hipSuccess) he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, g_aux);
+        // psi waits for the previous sub-batch's reductions to start: with the
+        // host running ahead, psi of later sub-batches would otherwise take the
+        // CUs that the reductions in flight need first
+        if (he == hipSuccess && ctx.gate) he = hipStreamWaitEvent(g_aux, ctx.gate, 0);
         (void)hipEventRecord(sb.ep, g_aux);
         const DevItem *dv = reinterpret_cast<const DevItem *>(db + sb.o_items);
         if (he == hipSuccess) he = launch_psi(dv, nlive, ctx.F->tgt.count, ctx.F->nsrc, g_aux);
@@ -851,6 +858,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
     }
     (void)hipEventRecord(sb.e0, stream);
+    ctx.gate = sb.e0;
     const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + sb.o_items);
     const int16_t *cu = reinterpret_cast<const int16_t *>(db + sb.o_cu);
     const int32_t *cgp = reinterpret_cast<const int32_t *>(db + sb.o_cg);
@@ -1138,8 +1146,7 @@ cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs
 cr_status cr_release(void) {
     std::lock_guard<std::mutex> lk(g_mutex);
     clear_graphs();
-    g_arenas[0].release();
-    g_arenas[1].release();
+    for (Arena &a : g_arenas) a.release();
     return CR_OK;
 }
 
@@ -1156,13 +1163,23 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     BatchCtx ctx;
     if (!ctx.init(fam, primes, coeffs, reinterpret_cast<hipStream_t>(hip_stream), err)) return fail(CR_EINVAL, err);
     ctx.out = {frob, frob_scaled, col_pole, col_prec, lpoly};
-    // Sub-batches: the host prepares sub-batch k + 1 while the device reduces sub-batch k.
-    const int S = count >= 192 ? 8 : (count >= 96 ? 4 : (count >= 48 ? 2 : 1));
+    // Sub-batches: the host prepares sub-batch k + 1 while the device reduces
+    // sub-batch k.  Sizes follow the width P of the host pool (each item's
+    // setup is one task): the first sub-batch, whose host setup and psi the
+    // device waits for, is one round of the pool (P items), the others two.
+    const int P = Pool::get().width();
+    std::vector<int> cut{0};
+    if (count <= 2 * P) {
+        cut.push_back(count);
+    } else {
+        cut.push_back(P);
+        while (cut.back() < count) cut.push_back(std::min(count, cut.back() + 2 * P));
+    }
+    const int S = (int)cut.size() - 1;
     std::vector<SubBatch> sub(S);
     for (int k = 0; k < S; k++) {
-        const int a = (int)((int64_t)count * k / S), z = (int)((int64_t)count * (k + 1) / S);
-        for (int i = a; i < z; i++) sub[k].idx.push_back(i);
-        sub[k].arena = k & 1;
+        for (int i = cut[k]; i < cut[k + 1]; i++) sub[k].idx.push_back(i);
+        sub[k].arena = k % kArenas;
     }
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
@@ -1173,13 +1190,15 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         if (g_aux) (void)hipStreamSynchronize(g_aux);
         for (int k = 0; k <= upto && k < S; k++) sub[k].destroy_events();
     };
+    // complete(k - kArenas + 1) releases the arena that sub-batch k + 1 reuses.
     for (int k = 0; k < S && fatal == CR_OK; k++) {
         fatal = prepare_sub(ctx, sub[k], fatal_msg);
         if (fatal == CR_OK) fatal = launch_sub(ctx, sub[k], fatal_msg);
-        if (fatal == CR_OK && k > 0) fatal = complete_sub(ctx, sub[k - 1], st, errs, fatal_msg);
+        if (fatal == CR_OK && k >= kArenas - 1) fatal = complete_sub(ctx, sub[k - (kArenas - 1)], st, errs, fatal_msg);
         if (fatal != CR_OK) stop_all(k);
     }
-    if (fatal == CR_OK) fatal = complete_sub(ctx, sub[S - 1], st, errs, fatal_msg);
+    for (int k = std::max(0, S - (kArenas - 1)); k < S && fatal == CR_OK; k++)
+        fatal = complete_sub(ctx, sub[k], st, errs, fatal_msg);
     if (fatal != CR_OK) {
         stop_all(S - 1);
         return fail(fatal, fatal_msg);

@@ -687,21 +687,26 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         std::vector<int> lev_of, rank_of;  // per distinct start term
         std::vector<u64> acc;              // nterm x b coefficients
         int col = 0;
+        std::vector<u64> scale(N);
         for (int m = 1; m <= n; m++) {
             const int sm = N + m - 1;
+            // scale_j = D_{j,m} (p s_m - 1)! / (p (m + j) - 1)!, the same for every column of pole m
+            u64 ratio = 1;
+            long long t = (long long)p * sm - 1;
+            for (int j = N - 1; j >= 0; j--) {
+                // D_{j,m} = (-1)^j sum_{i=j}^{N-1} C(m+i-1, i) C(i, j)
+                i128 Dj = 0;
+                for (int i = j; i < N; i++) Dj += (i128)binom(m + i - 1, i) * binom(i, j);
+                if (j & 1) Dj = -Dj;
+                i128 Dr = Dj % (i128)mq.q;
+                if (Dr < 0) Dr += (i128)mq.q;
+                for (; t >= (long long)p * (m + j); t--) ratio = mq.mul(ratio, (u64)t % mq.q);
+                scale[j] = mq.mul((u64)Dr, ratio);
+            }
             for (int bi = 0; bi < out.hodge[m - 1]; bi++, col++) {
                 const int8_t *beta = ksp[m].at(Bm[m][bi]);
                 for (int j = 0; j < N; j++) {
-                    // D_{j,m} = (-1)^j sum_{i=j}^{N-1} C(m+i-1, i) C(i, j)
-                    i128 Dj = 0;
-                    for (int i = j; i < N; i++) Dj += (i128)binom(m + i - 1, i) * binom(i, j);
-                    if (j & 1) Dj = -Dj;
-                    i128 Dr = Dj % (i128)mq.q;
-                    if (Dr < 0) Dr += (i128)mq.q;
-                    const int P = p * (m + j), L = m + j;
-                    u64 ratio = 1;  // (p s_m - 1)! / (P - 1)!
-                    for (long long t = P; t <= (long long)p * sm - 1; t++) ratio = mq.mul(ratio, (u64)t % mq.q);
-                    u64 scale = mq.mul((u64)Dr, ratio);
+                    const int L = m + j;
                     for (int a = 0; a < psp[j].count; a++) {
                         u64 C = fpow[j][a];
                         if (!C) continue;
@@ -715,7 +720,7 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                             acc.resize(acc.size() + b, 0);
                         }
                         u64 &v = acc[(size_t)sl * b + col];
-                        v = mq.add(v, mq.mul(scale, C));
+                        v = mq.add(v, mq.mul(scale[j], C));
                     }
                 }
             }
@@ -754,20 +759,25 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                 k++;
             }
     }
-    // unscaling constants (Section 2.5): (p s_m - 1)!/(n-1)! = p^v * unit
-    for (int c = 0; c < out.b; c++) {
-        const int m = out.col_pole[c], sm = out.N + m - 1;
-        const long long top = (long long)p * sm - 1;
-        int v = vp_fact(top, p);
+    // unscaling constants (Section 2.5): (p s_m - 1)!/(n-1)! = p^v * unit, per pole order m
+    std::vector<int> vm(n + 1, 0);
+    std::vector<u64> unitm(n + 1, 1);
+    for (int m = 1; m <= n; m++) {
+        const long long top = (long long)p * (out.N + m - 1) - 1;
+        vm[m] = vp_fact(top, p);
         u64 unit = 1;
         for (long long t = n; t <= top; t++) {
             long long x = t;
             while (x % p == 0) x /= p;
             unit = mq.mul(unit, (u64)x % mq.q);
         }
-        out.col_shift.push_back(v - (m - 1));
-        out.col_prec.push_back(out.M - (v - (m - 1)));
-        out.col_unit.push_back(unit);
+        unitm[m] = unit;
+    }
+    for (int c = 0; c < out.b; c++) {
+        const int m = out.col_pole[c];
+        out.col_shift.push_back(vm[m] - (m - 1));
+        out.col_prec.push_back(out.M - (vm[m] - (m - 1)));
+        out.col_unit.push_back(unitm[m]);
     }
     return CR_OK;
 }

@@ -61,9 +61,9 @@ __device__ static uint64_t inv_mod(const PMod &md, uint64_t a, uint32_t p, uint3
     return y;
 }
 
-// 256 threads of <= 64 VGPRs: a workgroup fits beside a reduction workgroup
-// on the same CU, so psi of the next sub-batch runs in the reduction's shadow
-constexpr int kPsiThreads = 256;
+// 16 waves per workgroup (4 per SIMD): the elimination is bound by the
+// latency of its LDS reads and 64-bit products, which the extra waves hide
+constexpr int kPsiThreads = 1024;
 constexpr int kPsiWaves = kPsiThreads / 64;
 
 // LDS: [J | I] (R x (C + R) u64), the pivot column snapshot (R u64), the
