@@ -950,14 +950,17 @@ __device__ __forceinline__ static void mfma5_products(const v4i (&A)[D][NKB], co
     }
 }
 
-// The finish of one output group of a tile's step is split into D pieces,
-// one per digit position k: z_k = sum over the group's slots of weight *
-// product sum, then one carry step.  Digits of continuing chains go to their
-// columns of the next planes, those of a chain that ends at this step are
-// parked at column r of its own rows there, everything else goes to the pad
-// column K.  The state between the pieces of a group is a FinState.
+// The finish of one output group of a tile's step is split into 1 + 2D
+// pieces: an init piece (slot weights, destination), then per digit position
+// k a gather piece (z_k = sum over the group's slots of weight * product sum)
+// and a carry piece.  Digits of continuing chains go to their columns of the
+// next planes, those of a chain that ends at this step are parked at column r
+// of its own rows there, everything else goes to the pad column K.  The state
+// between the pieces of a group is a FinState.
 struct FinState {
     int wt[3];
+    int zi;          // z_k (32-bit sums)
+    double zd;       // z_k (wider sums)
     double carry;
     int nz;          // OR of the digits: the balanced digits of 0 mod Q' are all 0
     int8_t *dst;
@@ -970,16 +973,19 @@ constexpr int slot_first(int nrt, int g) {  // first slot of output group g
     return t;
 }
 
+template <int D>
+constexpr int pieces_per_group() { return 1 + 2 * D; }
+
 template <int NRT, int NKB, int D, int NV, bool Z32, int P>
 __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const uint32_t (&sl)[16],
                                                    const TileState<NV> &ts, const int (&cols)[9], int8_t *row,
                                                    const DevDigitItem &it, FinState &fs, int &bad) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
-    constexpr int G = P / D, k = P % D;
+    constexpr int G = P / pieces_per_group<D>(), w = P % pieces_per_group<D>();
     constexpr int gs = slot_group(NRT, G);
     constexpr int j0 = slot_first(NRT, G);
-    if constexpr (k == 0) {
+    if constexpr (w == 0) {  // init
         const bool cont = ts.act && ts.more, ends = ts.act && !ts.more;
 #pragma unroll
         for (int m = 0; m < gs; m++) {
@@ -995,41 +1001,44 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         fs.carry = 0.0;
         fs.nz = 0;
         fs.chk = cont && rv && col < 0;
-    }
-    // carry step at position k: t = z_k + carry, carry = round(t / B),
-    // d_k = t - B carry (|d_k| <= (B-1)/2 since B is odd); the carry out of
-    // position D - 1 is a multiple of Q' and is dropped.  round() adds and
-    // subtracts 1.5 2^52; for |t| < 2^32 (Z32) its error (< 2^-23) cannot
-    // carry t / B across a half-integer (t / B lies at least 1 / (2B) from
-    // one), so it is exact; for wider sums a range test fixes the one-unit
-    // error it can make.
-    double t;
-    if constexpr (Z32) {
-        int z = 0;
+    } else if constexpr (w % 2 == 1) {  // gather of position k
+        constexpr int k = (w - 1) / 2;
+        if constexpr (Z32) {
+            int z = 0;
 #pragma unroll
-        for (int m = 0; m < gs; m++) z += __mul24(fs.wt[m], acc[k][j0 + m]);
-        t = (double)z + fs.carry;
-    } else {
-        double z = 0.0;
+            for (int m = 0; m < gs; m++) z += __mul24(fs.wt[m], acc[k][j0 + m]);
+            fs.zi = z;
+        } else {
+            double z = 0.0;
 #pragma unroll
-        for (int m = 0; m < gs; m++) z = fma((double)fs.wt[m], (double)acc[k][j0 + m], z);
-        t = z + fs.carry;
+            for (int m = 0; m < gs; m++) z = fma((double)fs.wt[m], (double)acc[k][j0 + m], z);
+            fs.zd = z;
+        }
+    } else {  // carry step at position k
+        constexpr int k = (w - 2) / 2;
+        // t = z_k + carry, carry = round(t / B), d_k = t - B carry (|d_k| <=
+        // (B-1)/2 since B is odd); the carry out of position D - 1 is a
+        // multiple of Q' and is dropped.  round() adds and subtracts 1.5 2^52;
+        // for |t| < 2^32 (Z32) its error (< 2^-23) cannot carry t / B across a
+        // half-integer (t / B lies at least 1 / (2B) from one), so it is exact;
+        // for wider sums a range test fixes the one-unit error it can make.
+        const double t = (Z32 ? (double)fs.zi : fs.zd) + fs.carry;
+        const double Bd = it.Bd, invB = 1.0 / Bd;
+        constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
+        double q = fma(t, invB, kRound) - kRound;
+        double dk = fma(-q, Bd, t);
+        if constexpr (!Z32) {
+            const double hB = (double)it.halfB;
+            const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
+            q += up1 - dn1;
+            dk += Bd * (dn1 - up1);
+        }
+        fs.carry = q;
+        const int di = (int)dk;
+        fs.nz |= di;
+        fs.dst[k * kCT * XS] = (int8_t)di;
+        if constexpr (k == D - 1) bad |= (fs.chk && fs.nz != 0) ? 2 : 0;
     }
-    const double Bd = it.Bd, invB = 1.0 / Bd;
-    constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
-    double q = fma(t, invB, kRound) - kRound;
-    double dk = fma(-q, Bd, t);
-    if constexpr (!Z32) {
-        const double hB = (double)it.halfB;
-        const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
-        q += up1 - dn1;
-        dk += Bd * (dn1 - up1);
-    }
-    fs.carry = q;
-    const int di = (int)dk;
-    fs.nz |= di;
-    fs.dst[k * kCT * XS] = (int8_t)di;
-    if constexpr (k == D - 1) bad |= (fs.chk && fs.nz != 0) ? 2 : 0;
 }
 
 template <int NRT, int NKB, int D, int NV, bool Z32, int P, int P1>
@@ -1084,7 +1093,7 @@ __device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const 
                     *reinterpret_cast<const v4i *>(Xp + ((J + 1) * kCT + c) * XS + b * 32 + half * 16);
         }
         accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[J & 1][kb], accP[i + J], 0, 0, 0);
-        constexpr int NP = slot_groups(NRT) * D;
+        constexpr int NP = slot_groups(NRT) * pieces_per_group<D>();
         mfma5_pieces<NRT, NKB, D, NV, Z32, U * NP / NU, (U + 1) * NP / NU>(accF, sl, tsF, cols, rowF, it, fs, bad);
         // plane clearing: NZ 16-byte stores per thread, spread over the phase
         constexpr int NT = 64 * NRT;
