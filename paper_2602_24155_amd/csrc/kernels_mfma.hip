@@ -930,6 +930,17 @@ __device__ __forceinline__ static void mfma5_advance(TileState<NV> &ts) {
     }
 }
 
+// One accumulator element of the finished tile, read straight from its
+// accumulation register (AGPR): this keeps the finished accumulator in AGPRs
+// while the other tile's MFMAs fill other AGPRs, instead of the whole
+// accumulator being copied to VGPRs before each phase.  Each element is read
+// at least one barrier after the MFMA that wrote it.
+__device__ __forceinline__ static int agpr_read(int x) {
+    int v;
+    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(v) : "a"(x));
+    return v;
+}
+
 template <int NKB, int D>
 __device__ __forceinline__ static void mfma5_products(const v4i (&A)[D][NKB], const int8_t *Xc, int c, int half,
                                                       v16i (&acc)[D]) {
@@ -1006,12 +1017,12 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         if constexpr (Z32) {
             int z = 0;
 #pragma unroll
-            for (int m = 0; m < gs; m++) z += __mul24(fs.wt[m], acc[k][j0 + m]);
+            for (int m = 0; m < gs; m++) z += __mul24(fs.wt[m], agpr_read(acc[k][j0 + m]));
             fs.zi = z;
         } else {
             double z = 0.0;
 #pragma unroll
-            for (int m = 0; m < gs; m++) z = fma((double)fs.wt[m], (double)acc[k][j0 + m], z);
+            for (int m = 0; m < gs; m++) z = fma((double)fs.wt[m], (double)agpr_read(acc[k][j0 + m]), z);
             fs.zd = z;
         }
     } else {  // carry step at position k
