@@ -613,29 +613,26 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                 err = "Griffiths-Dwork system not solvable";
                 return CR_ESELFCHECK;
             }
+            // at m = n, Pm is the identity on Homog_{dn-n-1} (K is that space)
+            const bool ident = m == n && K.count == F;
+            auto times_pm = [&](int row, int t) -> u64 {  // (X Pm)[row, t]
+                if (ident) return X[(size_t)row * K.count + t];
+                u128 acc = 0;
+                for (int k = 0; k < K.count; k++) {
+                    acc += (u128)X[(size_t)row * K.count + k] * Pm[(size_t)k * F + t];
+                    if ((k & 127) == 127) acc = mq.reduce(acc);
+                }
+                return mq.reduce(acc);
+            };
             // coordinates of B_m: rows ngen..ngen+hm-1 of X, composed with Pm
             for (int j = 0; j < hm; j++)
-                for (int t = 0; t < F; t++) {
-                    u128 acc = 0;
-                    for (int k = 0; k < K.count; k++) {
-                        acc += (u128)X[(size_t)(ngen + j) * K.count + k] * Pm[(size_t)k * F + t];
-                        if ((k & 127) == 127) acc = mq.reduce(acc);
-                    }
-                    out.rho[(size_t)(rowoff[m] + j) * F + t] = mq.reduce(acc);
-                }
+                for (int t = 0; t < F; t++) out.rho[(size_t)(rowoff[m] + j) * F + t] = times_pm(ngen + j, t);
             if (m == 1) break;
             // P_{m-1} = (m-1)^{-1} * Deriv * X[0..ngen) * Pm
             const MonoSpace &K2 = ksp[m - 1];
             std::vector<u64> AP((size_t)ngen * F, 0);
             for (int c = 0; c < ngen; c++)
-                for (int t = 0; t < F; t++) {
-                    u128 acc = 0;
-                    for (int k = 0; k < K.count; k++) {
-                        acc += (u128)X[(size_t)c * K.count + k] * Pm[(size_t)k * F + t];
-                        if ((k & 127) == 127) acc = mq.reduce(acc);
-                    }
-                    AP[(size_t)c * F + t] = mq.reduce(acc);
-                }
+                for (int t = 0; t < F; t++) AP[(size_t)c * F + t] = times_pm(c, t);
             std::vector<u64> Pn((size_t)std::max(K2.count, 1) * F, 0);
             u64 inv = mq.inv((u64)(m - 1));
             int e[kMaxVars];
@@ -703,13 +700,18 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                 for (; t >= (long long)p * (m + j); t--) ratio = mq.mul(ratio, (u64)t % mq.q);
                 scale[j] = mq.mul((u64)Dr, ratio);
             }
+            // scale_j f^j, shared by the columns of pole m
+            std::vector<std::vector<u64>> sf(N);
+            for (int j = 0; j < N; j++) {
+                sf[j].resize(psp[j].count);
+                for (int a = 0; a < psp[j].count; a++) sf[j][a] = fpow[j][a] ? mq.mul(scale[j], fpow[j][a]) : 0;
+            }
             for (int bi = 0; bi < out.hodge[m - 1]; bi++, col++) {
                 const int8_t *beta = ksp[m].at(Bm[m][bi]);
                 for (int j = 0; j < N; j++) {
                     const int L = m + j;
                     for (int a = 0; a < psp[j].count; a++) {
-                        u64 C = fpow[j][a];
-                        if (!C) continue;
+                        if (!fpow[j][a]) continue;
                         for (int i = 0; i < nv; i++) e[i] = beta[i] + psp[j].at(a)[i];
                         const int rk = lsp[L].rank(e);
                         int &sl = slot[L][rk];
@@ -720,7 +722,7 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
                             acc.resize(acc.size() + b, 0);
                         }
                         u64 &v = acc[(size_t)sl * b + col];
-                        v = mq.add(v, mq.mul(scale[j], C));
+                        v = mq.add(v, sf[j][a]);
                     }
                 }
             }
