@@ -1078,12 +1078,26 @@ struct UnitMap {
         for (int q = 0; q < J; q++) t += (D - q) * NKB;
         return t;
     }
+    // The operands of plane J (J >= 1) are read from LDS kLead units before
+    // the plane starts (never before plane J - 1 starts: the buffer they go to
+    // is plane J - 2's): far enough ahead to hide the LDS latency, close
+    // enough that few digit stores of the finishing work are issued in between
+    // (the LDS counter tracks at most 15 outstanding operations).
+    static constexpr int kLead = 4;
+    static constexpr int load_unit(int J) {
+        const int u = first(J) - kLead;
+        return u > first(J - 1) ? u : first(J - 1);
+    }
+    static constexpr int plane_loaded_at(int u) {  // plane whose operands unit u reads, or -1
+        for (int J = 1; J < D; J++)
+            if (load_unit(J) == u) return J;
+        return -1;
+    }
 };
 
 // One unit of a phase: the MFMA of tile P's unit U, the finishing pieces of
 // tile F and the plane clearing stores that fall on it, then a scheduling
 // fence, so that each MFMA runs in the shadow of independent vector work.
-// The operands of plane J + 1 are read from LDS when plane J starts.
 template <int NRT, int NKB, int D, int NV, bool Z32, int U>
 __device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
                                                   v4i (&xb)[2][NKB], v16i (&accP)[D], const v16i (&accF)[D],
@@ -1097,11 +1111,11 @@ __device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const 
         constexpr int J = UM::plane(U);
         constexpr int w = U - UM::first(J);
         constexpr int kb = w / (D - J), i = w % (D - J);
-        if constexpr (w == 0 && J + 1 < D) {
+        constexpr int JL = UM::plane_loaded_at(U);
+        if constexpr (JL > 0) {
 #pragma unroll
             for (int b = 0; b < NKB; b++)
-                xb[(J + 1) & 1][b] =
-                    *reinterpret_cast<const v4i *>(Xp + ((J + 1) * kCT + c) * XS + b * 32 + half * 16);
+                xb[JL & 1][b] = *reinterpret_cast<const v4i *>(Xp + (JL * kCT + c) * XS + b * 32 + half * 16);
         }
         accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[J & 1][kb], accP[i + J], 0, 0, 0);
         constexpr int NP = slot_groups(NRT) * pieces_per_group<D>();
