@@ -363,35 +363,19 @@ __device__ __forceinline__ static int div_small(int u, int v) {
     return q;
 }
 
-// Lookup tables of the pair kernel, built once per workgroup in LDS (3
-// variables): dirIdx[v0 + (d+1) v1] = index of the direction (v0, v1,
-// d - v0 - v1) in the family's list (-1 if absent); finIdx[u0 + 3 u1 + 9 u2]
-// = index of the final exponent (u0, u1, u2) (-1 if absent; final exponents
-// have |U| = |S| - 1 <= 2).
-constexpr int kDirLut = 512;
-constexpr int kFinLut = 32;
-
-__device__ static void build_luts3(const DevFamily &fam, int8_t *dirIdxL, int8_t *finIdxL, int tid, int nt) {
-    const int d1 = fam.d + 1;
-    for (int key = tid; key < d1 * d1; key += nt) {
-        const int v0 = key % d1, v1 = key / d1, v2 = fam.d - v0 - v1;
-        int t = -1;
-        for (int a = 0; a < fam.ndir && t < 0 && v2 >= 0; a++)
-            if (fam.dirs[a * 3] == v0 && fam.dirs[a * 3 + 1] == v1 && fam.dirs[a * 3 + 2] == v2) t = a;
-        dirIdxL[key] = (int8_t)t;
-    }
-    for (int key = tid; key < 27; key += nt) {
-        const int u0 = key % 3, u1 = (key / 3) % 3, u2 = key / 9;
-        int t = -1;
-        for (int a = 0; a < fam.nfinU && t < 0; a++)
-            if (fam.finU[a * 3] == u0 && fam.finU[a * 3 + 1] == u1 && fam.finU[a * 3 + 2] == u2) t = a;
-        finIdxL[key] = (int8_t)t;
-    }
+// Index of (v0, v1, deg - v0 - v1) among the monomials of degree deg in 3
+// variables in lexicographically descending order, which is the family's
+// order of directions (degree d) and of final exponents (degree |S| - 1): the
+// monomials before it have a larger first exponent, (deg - v0)(deg - v0 + 1)/2
+// of them, or the same first and a larger second one, deg - v0 - v1.
+__device__ __forceinline__ static int mono_rank3(int v0, int v1, int deg) {
+    const int r = deg - v0;
+    return r * (r + 1) / 2 + (r - v1);
 }
 
-// choose_chunk_reg for 3 variables with the direction found through dirIdx
-__device__ __forceinline__ static void choose_chunk_lut3(const DevFamily &fam, const int8_t *dirIdxL, const int *U,
-                                                         int poles_left, int *v, int &dir, int &k) {
+// choose_chunk_reg for 3 variables with the direction index in closed form
+__device__ __forceinline__ static void choose_chunk3(const DevFamily &fam, const int *U, int poles_left, int *v,
+                                                     int &dir, int &k) {
     int left = fam.d;
 #pragma unroll
     for (int i = 0; i < 3; i++) v[i] = 0;
@@ -416,13 +400,14 @@ __device__ __forceinline__ static void choose_chunk_lut3(const DevFamily &fam, c
 #pragma unroll
     for (int i = 0; i < 3; i++)
         if (v[i]) k = min(k, div_small(U[i], v[i]));
-    dir = left == 0 ? dirIdxL[v[0] + (fam.d + 1) * v[1]] : -1;
+    dir = left == 0 ? mono_rank3(v[0], v[1], fam.d) : -1;
 }
 
-// final-exponent index of U (3 variables), -1 if U is not one
-__device__ __forceinline__ static int fin_index3(const int8_t *finIdxL, const int *U) {
-    const bool ok = (unsigned)U[0] < 3u && (unsigned)U[1] < 3u && (unsigned)U[2] < 3u;
-    return ok ? finIdxL[U[0] + 3 * U[1] + 9 * U[2]] : -1;
+// final-exponent index of U (3 variables, |U| = |S| - 1), -1 if U is not one
+__device__ __forceinline__ static int fin_index3(const DevFamily &fam, const int *U) {
+    const int deg = __popc(fam.smask & 7u) - 1;
+    const bool ok = U[0] >= 0 && U[1] >= 0 && U[2] >= 0 && U[0] + U[1] + U[2] == deg;
+    return ok ? mono_rank3(U[0], U[1], deg) : -1;
 }
 
 // Balanced base-B digits of x (0 <= x < Q') written to the D digit planes at xp
@@ -824,9 +809,8 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
                                   const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                                   const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
                                   uint64_t *__restrict__ store, int *__restrict__ err, int8_t *X,
-                                  const int16_t *colmapL, const int8_t *dirsL, const int8_t *dirIdxL,
-                                  TileState<NV> &ts) {
-    static_assert(NV == 3, "lookup tables are built for 3 variables");
+                                  const int16_t *colmapL, const int8_t *dirsL, TileState<NV> &ts) {
+    static_assert(NV == 3, "the direction index is in closed form for 3 variables");
     constexpr int XS = NKB * 32 + 16;
     const int s = fam.s, n = fam.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -853,7 +837,7 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
 #pragma unroll
         for (int i = 0; i < NV; i++) ts.V[i] = dirsL[d0 * NV + i];
     } else {
-        choose_chunk_lut3(fam, dirIdxL, ts.U, ts.pole - ts.pend, ts.V, d0, k0);
+        choose_chunk3(fam, ts.U, ts.pole - ts.pend, ts.V, d0, k0);
     }
     if (d0 < 0 || k0 < 1) {
         if (wave == 0 && half == 0) atomicOr(err, 1);
@@ -886,8 +870,7 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
 
 // exponent after the step, next direction and chunk, final-exponent row
 template <int NV>
-__device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const int8_t *dirIdxL,
-                                                  const int8_t *finIdxL, TileState<NV> &ts, int &bad) {
+__device__ __forceinline__ static void mfma5_book(const DevFamily &fam, TileState<NV> &ts, int &bad) {
     ts.act = ts.pole > ts.pend;
     ts.dirn = ts.dir;
     ts.kleftn = ts.kleft - 1;
@@ -899,7 +882,7 @@ __device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const in
     ts.more = ts.act && ts.pole - 1 > ts.pend;
     if (ts.more && ts.kleftn == 0) {
         int d0, k0;
-        choose_chunk_lut3(fam, dirIdxL, ts.up, ts.pole - 1 - ts.pend, ts.Vn, d0, k0);
+        choose_chunk3(fam, ts.up, ts.pole - 1 - ts.pend, ts.Vn, d0, k0);
         if (d0 < 0 || k0 < 1) {
             bad |= 1;
             d0 = 0;
@@ -910,7 +893,7 @@ __device__ __forceinline__ static void mfma5_book(const DevFamily &fam, const in
     }
     ts.fin_row = -1;
     if (ts.act && !ts.more && ts.vout < 0) {
-        const int Ui = fin_index3(finIdxL, ts.up);
+        const int Ui = fin_index3(fam, ts.up);
         if (Ui < 0) bad |= 4;
         else ts.fin_row = Ui * fam.s;
     }
@@ -1127,7 +1110,8 @@ __device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const 
         static_assert(NU >= NZ, "clearing stores per phase");
         if constexpr (U % (NU / NZ) == 0 && U / (NU / NZ) < NZ) {
             constexpr int zq = U / (NU / NZ);
-            if (zq * NT + tid < N16) Xz[zq * NT + tid] = v4i{0, 0, 0, 0};
+            if constexpr (N16 % NT == 0) Xz[zq * NT + tid] = v4i{0, 0, 0, 0};
+            else if (zq * NT + tid < N16) Xz[zq * NT + tid] = v4i{0, 0, 0, 0};
         }
         __builtin_amdgcn_sched_barrier(0);
         mfma5_unit<NRT, NKB, D, NV, Z32, U + 1>(A, Xp, c, half, xb, accP, accF, sl, tsF, cols, rowF, it, fs, Xz, tid,
@@ -1190,7 +1174,7 @@ __device__ __forceinline__ static void mfma5_flush(const DevFamily &fam, const T
 
 template <int NRT, int NKB, int D>
 constexpr size_t mfma5_lds_bytes() {
-    return (size_t)4 * D * kCT * (NKB * 32 + 16) + kTabCap * 2 + 512 + kDirLut + kFinLut;
+    return (size_t)4 * D * kCT * (NKB * 32 + 16) + kTabCap * 2 + 512;
 }
 
 // One pair of tiles (tiles[0], tiles[1]: same item) on the LDS at lds.
@@ -1199,8 +1183,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
                                   const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                                   const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
                                   uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf, const uint32_t (&sl)[16],
-                                  int *__restrict__ err, int8_t *Xall, const int16_t *colmapL, const int8_t *dirsL,
-                                  const int8_t *dirIdxL, const int8_t *finIdxL) {
+                                  int *__restrict__ err, int8_t *Xall, const int16_t *colmapL, const int8_t *dirsL) {
     constexpr int K = NKB * 32;
     constexpr int XS = K + 16;
     constexpr int NT = 64 * NRT;
@@ -1231,8 +1214,8 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     }
     __syncthreads();
     TileState<NV> sA, sB;
-    mfma5_init<NRT, NKB, D, NV>(fam, tA, it, cu, cg, cpole, vx, store, err, XA, colmapL, dirsL, dirIdxL, sA);
-    mfma5_init<NRT, NKB, D, NV>(fam, tB, it, cu, cg, cpole, vx, store, err, XBp, colmapL, dirsL, dirIdxL, sB);
+    mfma5_init<NRT, NKB, D, NV>(fam, tA, it, cu, cg, cpole, vx, store, err, XA, colmapL, dirsL, sA);
+    mfma5_init<NRT, NKB, D, NV>(fam, tB, it, cu, cg, cpole, vx, store, err, XBp, colmapL, dirsL, sB);
     __syncthreads();
 
     int bad = 0, ca = 0, cb = 0;
@@ -1241,7 +1224,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     const int steps = max(tA.steps, tB.steps);
     for (int step = 0; step < steps; step++) {
         // phase 1: products of B || finish of A
-        mfma5_book<NV>(fam, dirIdxL, finIdxL, sA, bad);
+        mfma5_book<NV>(fam, sA, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XBp + cb * XB, c, half, accB, accA, sl, sA, colmapL + sA.dirn * s,
                                           XA + (ca ^ 1) * XB + c * XS, it, XA + ca * XB, tid, bad);
         __syncthreads();
@@ -1249,7 +1232,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
         mfma5_advance<NV>(sA);
         ca ^= 1;
         // phase 2: products of A (next step) || finish of B
-        mfma5_book<NV>(fam, dirIdxL, finIdxL, sB, bad);
+        mfma5_book<NV>(fam, sB, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XA + ca * XB, c, half, accA, accB, sl, sB, colmapL + sB.dirn * s,
                                           XBp + (cb ^ 1) * XB + c * XS, it, XBp + cb * XB, tid, bad);
         __syncthreads();
@@ -1275,15 +1258,12 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma5(DevFamily fam, const 
     int8_t *Xall = reinterpret_cast<int8_t *>(lds5);
     int16_t *colmapL = reinterpret_cast<int16_t *>(lds5 + 4 * XB);
     int8_t *dirsL = reinterpret_cast<int8_t *>(colmapL + kTabCap);
-    int8_t *dirIdxL = dirsL + 512;
-    int8_t *finIdxL = dirIdxL + kDirLut;
     __shared__ int next;
     uint32_t sl[16];
     mfma4_prologue<NRT, NKB, D, NV, Z32>(fam, slots, sl, colmapL, dirsL);
-    build_luts3(fam, dirIdxL, finIdxL, threadIdx.x, 64 * NRT);  // published by the pair's first barrier
     if (!queue) {  // one pair per workgroup
         mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * blockIdx.x, items, cu, cg, cpole, vx, store, hbuf, sl, err,
-                                         Xall, colmapL, dirsL, dirIdxL, finIdxL);
+                                         Xall, colmapL, dirsL);
         return;
     }
     for (;;) {  // persistent: pairs drained through the counter
@@ -1293,7 +1273,7 @@ __global__ __launch_bounds__(64 * NRT) void k_reduce_mfma5(DevFamily fam, const 
         __syncthreads();
         if (pi >= npairs) break;
         mfma5_pair<NRT, NKB, D, NV, Z32>(fam, tiles + 2 * pi, items, cu, cg, cpole, vx, store, hbuf, sl, err, Xall,
-                                         colmapL, dirsL, dirIdxL, finIdxL);
+                                         colmapL, dirsL);
     }
 }
 
@@ -1406,8 +1386,6 @@ bool mfma5_supports(const DevFamily &fam, int D) {
     mfma4_shape(fam, nrt, nkb);
     // the digits of an ending chain are parked at columns r < s of its rows
     if (fam.s > nkb * 32) return false;
-    // direction and final-exponent lookup tables (3 variables, |U| = 2 at the end)
-    if ((fam.d + 1) * (fam.d + 1) > kDirLut || fam.ndir > 127 || fam.nfinU > 127) return false;
     return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));
 }
 

@@ -97,3 +97,19 @@ def test_family_options_are_validated():
     with pytest.raises(C.CrError) as e:
         C.cr_autotune(C.family(3, 5), [31], [[1] * 21], trials=0)
     assert e.value.status == C.CR_EINVAL
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 4, 5, 6, 8])
+def test_closed_form_rank_of_three_variable_monomials(d):
+    """The pair kernel finds a direction's index (degree d) and a final
+    exponent's index (degree |S| - 1 <= 2) by the closed form
+    (d - v0)(d - v0 + 1)/2 + (d - v0 - v1); it must agree with the monomial
+    order of the library (degrees it takes as a family) and of the oracle
+    (every degree), which test_monomials_and_dims ties together."""
+    orders = [monomials(3, d)]
+    if d >= 3:
+        orders.append([tuple(int(x) for x in m) for m in C.cr_monomials(3, d)])
+    for mons in orders:
+        for idx, m in enumerate(mons):
+            r = d - m[0]
+            assert r * (r + 1) // 2 + (r - m[1]) == idx
