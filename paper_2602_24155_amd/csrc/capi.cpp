@@ -496,8 +496,10 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             sb.st[i] = CR_ESELFCHECK;
             sb.errs[i] = "basis size differs from the Hodge numbers";
         }
+        // depth-first: the device runs Algorithm 3; the chunk count is taken
+        // in complete_sub, while the device works
         if (sb.st[i] == CR_OK && policy != CR_POLICY_LEARNED &&
-            !plan_item(F, sb.items[i], policy, sb.plans[i], sb.errs[i]))
+            !plan_item(F, sb.items[i], policy, sb.plans[i], sb.errs[i], policy != CR_POLICY_DEPTH_FIRST))
             sb.st[i] = CR_EINVAL;
         if (sb.st[i] == CR_OK && ctx.want_mfma) {
             ItemSetup &it = sb.items[i];
@@ -972,6 +974,11 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
         errs[sb.idx[i]] = sb.errs[i];
     }
     if (sb.live.empty()) return CR_OK;
+    if (ctx.policy == CR_POLICY_DEPTH_FIRST)
+        parallel_for((int)sb.live.size(), [&](int li) {
+            const int i = sb.live[li];
+            sb.plans[i].chunks = std::max<int64_t>(0, depth_first_chunks(*ctx.F, sb.items[i]));
+        });
     // edone follows the downloads of this sub-batch only (later sub-batches may still run)
     hipError_t he = hipEventSynchronize(sb.edone);
     if (he == hipSuccess) {

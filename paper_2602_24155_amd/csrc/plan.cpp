@@ -114,7 +114,8 @@ void init_terms(const Family &fam, const ItemSetup &it, std::vector<PlanTerm> &t
 // u[var] reaches 0 if var >= 0; or the forced direction dirs[a] >= 0 for the
 // whole range) and appends the phase's vectors to the plan.
 bool run_phase(const Family &fam, ItemPlan &plan, std::vector<PlanTerm> &terms, const std::vector<int> &active,
-               const std::vector<int> &stops, int var, const std::vector<int32_t> *forced, std::string &err) {
+               const std::vector<int> &stops, int var, const std::vector<int32_t> *forced, std::string &err,
+               bool simulate = true) {
     const int nv = fam.nv, n = fam.n;
     std::vector<PlanVec> vecs;
     for (size_t a = 0; a < active.size(); a++) {
@@ -143,8 +144,10 @@ bool run_phase(const Family &fam, ItemPlan &plan, std::vector<PlanTerm> &terms, 
             reached = stops[a];
             plan.chunks++;
             pv.dir = fd;
-        } else {
+        } else if (simulate || var >= 0) {
             reached = greedy_run(fam, U, t.pole, stops[a], var, plan.chunks);
+        } else {
+            reached = stops[a];  // Algorithm 3 runs on the device
         }
         if (reached < 0) {
             err = "no valid reduction direction (Algorithm 3)";
@@ -347,7 +350,18 @@ bool PChunkPlanner::end_phase(const std::vector<int32_t> &dir, std::string &err)
     return true;
 }
 
-bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err) {
+int64_t depth_first_chunks(const Family &fam, const ItemSetup &it) {
+    int64_t chunks = 0;
+    for (int k = 0; k < it.nchain(); k++) {
+        int U[kMaxVars] = {0};
+        for (int i = 0; i < fam.nv; i++) U[i] = it.chain_u[(size_t)k * fam.nv + i];
+        if (greedy_run(fam, U, it.chain_pole[k], fam.n, -1, chunks) != fam.n) return -1;
+    }
+    return chunks;
+}
+
+bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err,
+               bool count_chunks) {
     const int nv = fam.nv, n = fam.n, nch = it.nchain();
     if (policy == CR_POLICY_P_CHUNK) {
         PChunkPlanner pc;
@@ -367,7 +381,7 @@ bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &pla
     if (policy == CR_POLICY_DEPTH_FIRST) {
         std::vector<int> act(nch), stops(nch, n);
         for (int k = 0; k < nch; k++) act[k] = k;
-        return run_phase(fam, plan, terms, act, stops, -1, nullptr, err);
+        return run_phase(fam, plan, terms, act, stops, -1, nullptr, err, count_chunks);
     }
     if (policy == CR_POLICY_VAR_BY_VAR) {
         if (it.b > 64) {

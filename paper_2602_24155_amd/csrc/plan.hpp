@@ -114,7 +114,14 @@ int direction_index(const Family &fam, const int *v);
 bool direction_valid(const Family &fam, const int *U, const int *v, int k);
 
 // Builds the plan of one item for a plain policy (depth-first, p-chunk,
-// var-by-var).  Requires b <= 64 for the combining policies.
-bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err);
+// var-by-var).  Requires b <= 64 for the combining policies.  With
+// count_chunks false, the depth-first plan does not run Algorithm 3 along
+// every chain (the device chooses the directions itself): plan.chunks stays 0
+// and depth_first_chunks() gives it later.
+bool plan_item(const Family &fam, const ItemSetup &it, int policy, ItemPlan &plan, std::string &err,
+               bool count_chunks = true);
+// Algorithm 3 chunks of the depth-first reduction of every start vector of
+// the item to pole n; -1 if some vector has no valid direction.
+int64_t depth_first_chunks(const Family &fam, const ItemSetup &it);
 
 }  // namespace crf
