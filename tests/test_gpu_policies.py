@@ -56,3 +56,19 @@ def test_full_size_policies_agree():
         assert np.array_equal(res["scaled"], base["scaled"])
         assert res["lpoly"] == base["lpoly"]
         assert res["stats"].column_steps < base["stats"].column_steps
+
+
+@pytest.mark.parametrize("policy", [C.CR_POLICY_DEPTH_FIRST] + COMBINING)
+def test_batch_counters_match_the_host_game(policy):
+    """The counters of a batch call (the depth-first chunk count is taken while
+    the device runs) equal the sums of cr_policy_cost over its items."""
+    items = workload_items("quintic_curves_mixed", range(40))
+    res = run_batch(3, 5, items, policy=policy)
+    fam = C.family(3, 5, policy=policy)
+    want = {k: 0 for k in ("column_steps", "chunks", "vectors", "merged_terms")}
+    for p, c in items:
+        cost = C.cr_policy_cost(fam, p, c)
+        for k in want:
+            want[k] += getattr(cost, k)
+    for k, v in want.items():
+        assert getattr(res["stats"], k) == v, k
