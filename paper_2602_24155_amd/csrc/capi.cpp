@@ -46,7 +46,7 @@ hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, 
                                uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, bool z32,
                                int pgrid, int *queue, hipStream_t stream);
 size_t psi_lds_bytes(int R, int C);
-hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, hipStream_t stream);
+hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream);
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
                            int nrt, int nkb, int T, int nsrc, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
@@ -117,6 +117,7 @@ struct FamilyEntry {
 std::mutex g_mutex;
 constexpr int kArenas = 2;
 Arena g_arenas[kArenas];  // sub-batch k of a call uses arena k mod kArenas
+Arena g_psi_arena;         // psi of every hypersurface of a call (device psi)
 std::map<std::string, hipGraphExec_t> g_graphs;  // captured reduction launches by launch signature
 hipStream_t g_capture = nullptr;                 // private stream used for graph capture
 hipStream_t g_aux = nullptr;                     // upload and psi of the next sub-batch
@@ -393,7 +394,10 @@ struct BatchCtx {
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
-    hipEvent_t gate = nullptr;  // start of the last launched sub-batch's reductions (main stream)
+    // device psi: one k_psi launch for every item of the call, at its start
+    uint64_t *psi_dev = nullptr;         // count x (nsrc x T), caller's item order
+    const int32_t *psi_flags = nullptr;  // host copy of k_psi's per-item flags (after psi_done)
+    hipEvent_t psi_t0 = nullptr, psi_done = nullptr;
     const int32_t *primes = nullptr;
     const uint32_t *coeffs = nullptr;
     Outputs out{};
@@ -656,7 +660,6 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         if (!dpsi)
             for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     }
-    const size_t o_J = take(dpsi ? 8 * psi_len * nlive : 0);
     const size_t o_rho = take(8 * rho_len * nlive);
     const size_t o_coef = take(8 * ncoef);
     sb.o_cu = take(2 * (size_t)F.nv * nvec);
@@ -670,7 +673,6 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     const size_t o_frow = take(4 * std::max<size_t>(nfin_all, 1));
     sb.o_err = take(4 * (1 + (size_t)nlive));  // error bits, then one k_psi flag per item
     sb.h_end = off;  // everything above is uploaded
-    sb.o_psi_dev = take(dpsi ? 8 * psi_len * nlive : 0);
     if (sb.use_mfma && dpsi)
         for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     sb.o_queue = take(4 * std::max<size_t>(sb.launches.size(), 1));
@@ -743,10 +745,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         di.p = it.p;
         di.flag = reinterpret_cast<int32_t *>(db + sb.o_err) + 1 + li;
         if (dpsi) {
-            di.J = reinterpret_cast<const uint64_t *>(db + o_J) + psi_len * li;
-            di.psi_out = reinterpret_cast<uint64_t *>(db + sb.o_psi_dev) + psi_len * li;
+            di.psi_out = ctx.psi_dev + psi_len * (size_t)sb.idx[sb.live[li]];
             di.psi = di.psi_out;
-            std::memcpy(hb + o_J + 8 * psi_len * li, it.J.data(), 8 * psi_len);
         } else {
             di.psi = reinterpret_cast<const uint64_t *>(db + o_psi) + psi_len * li;
         }
@@ -835,21 +835,14 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     (void)hipEventCreateWithFlags(&sb.edone, hipEventDisableTiming);
     hipError_t he = hipSuccess;
     if (ctx.device_psi) {
-        // upload, psi of every item and (MFMA path) its digits in the kernel's
-        // fragment order on the auxiliary stream: this overlaps the reduction of
-        // the previous sub-batches (whose arenas are the other ones); the main stream
-        // waits for it before the reductions
+        // upload and (MFMA path) the digits of psi in the kernel's fragment
+        // order on the auxiliary stream, behind the call's k_psi launch; this
+        // overlaps the reduction of the previous sub-batch (whose arena is the
+        // other one); the main stream waits for it before the reductions
         if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
-        (void)hipEventCreate(&sb.ep);
         (void)hipEventCreate(&sb.epe);
         if (he == hipSuccess) he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, g_aux);
-        // psi waits for the previous sub-batch's reductions to start: with the
-        // host running ahead, psi of later sub-batches would otherwise take the
-        // CUs that the reductions in flight need first
-        if (he == hipSuccess && ctx.gate) he = hipStreamWaitEvent(g_aux, ctx.gate, 0);
-        (void)hipEventRecord(sb.ep, g_aux);
         const DevItem *dv = reinterpret_cast<const DevItem *>(db + sb.o_items);
-        if (he == hipSuccess) he = launch_psi(dv, nlive, ctx.F->tgt.count, ctx.F->nsrc, g_aux);
         if (he == hipSuccess && sb.use_mfma)
             he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
                                  reinterpret_cast<const int16_t *>(db + sb.o_tables + ctx.fe->off_slot_src), ctx.nrt,
@@ -860,7 +853,6 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
     }
     (void)hipEventRecord(sb.e0, stream);
-    ctx.gate = sb.e0;
     const DevItem *ditems_v = reinterpret_cast<const DevItem *>(db + sb.o_items);
     const int16_t *cu = reinterpret_cast<const int16_t *>(db + sb.o_cu);
     const int32_t *cgp = reinterpret_cast<const int32_t *>(db + sb.o_cg);
@@ -1011,7 +1003,7 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
     parallel_for((int)sb.live.size(), [&](int li) {
         const int i = sb.live[li], g = sb.idx[i];
         const size_t bb = (size_t)b * b;
-        if (flags[li]) {
+        if (flags[li] || (ctx.psi_flags && ctx.psi_flags[g])) {
             st[g] = CR_ESINGULAR;
             errs[g] = "J_S is not surjective mod p (no unit pivot)";
             return;
@@ -1154,6 +1146,88 @@ cr_status cr_release(void) {
     std::lock_guard<std::mutex> lk(g_mutex);
     clear_graphs();
     for (Arena &a : g_arenas) a.release();
+    g_psi_arena.release();
+    return CR_OK;
+}
+
+// psi of every item of a call in one k_psi launch on the auxiliary stream
+// (J_S is built on the device from the coefficients), started before the
+// first sub-batch's host setup.  Items whose prime the setup will reject get
+// q = 0 and are skipped by the kernel.
+cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
+    const Family &F = *ctx.F;
+    const size_t psi_len = (size_t)F.nsrc * F.tgt.count;
+    const int nco = ctx.nco, n = F.n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const size_t o_jtab = take(4 * F.jtab.size());
+    const size_t o_coef = take(4 * (size_t)count * nco);
+    const size_t o_items = take(sizeof(DevItem) * count);
+    const size_t o_flags = take(4 * (size_t)count);
+    const size_t h_end = off;
+    const size_t o_psi = take(8 * psi_len * count);
+    if (!g_psi_arena.ensure(off, h_end)) {
+        msg = "device or pinned host allocation failed";
+        return CR_ENOMEM;
+    }
+    unsigned char *hb = static_cast<unsigned char *>(g_psi_arena.host);
+    unsigned char *db = static_cast<unsigned char *>(g_psi_arena.dev);
+    std::memcpy(hb + o_jtab, F.jtab.data(), 4 * F.jtab.size());
+    std::memcpy(hb + o_coef, ctx.coeffs, 4 * (size_t)count * nco);
+    std::memset(hb + o_flags, 0, 4 * (size_t)count);
+    std::vector<int> hodge(n);
+    for (int m = 1; m <= n; m++) hodge[m - 1] = (int)hodge_size(F.nv, F.d, m);
+    std::map<int, ModQ> mods;  // prime -> q = p^M (0 when the setup rejects the prime)
+    DevItem *hit = reinterpret_cast<DevItem *>(hb + o_items);
+    for (int g = 0; g < count; g++) {
+        const int p = ctx.primes[g];
+        auto m = mods.find(p);
+        if (m == mods.end()) {
+            ModQ mq;
+            bool prime = p >= 2;
+            for (int t = 2; t * t <= p && prime; t++) prime = p % t != 0;
+            int rr, NN, MM;
+            std::string e2;
+            if (prime && p >= 7 && p < 50 && p > n && F.d % p != 0 &&
+                choose_precision(p, n, hodge, ctx.fam->r, ctx.fam->n_series, rr, NN, MM, e2)) {
+                u64 q = 1;
+                for (int k = 0; k < MM; k++) q *= (u64)p;
+                mq.init(q);
+            }
+            m = mods.emplace(p, mq).first;
+        }
+        DevItem &di = hit[g];
+        std::memset(&di, 0, sizeof(di));
+        di.q = m->second.q;
+        di.mu = m->second.mu;
+        di.sbits = m->second.sbits;
+        di.p = p;
+        di.fcoef = reinterpret_cast<const uint32_t *>(db + o_coef) + (size_t)g * nco;
+        di.psi_out = reinterpret_cast<uint64_t *>(db + o_psi) + psi_len * g;
+        di.flag = reinterpret_cast<int32_t *>(db + o_flags) + g;
+    }
+    hipError_t he = hipSuccess;
+    if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
+    (void)hipEventCreate(&ctx.psi_t0);
+    (void)hipEventCreate(&ctx.psi_done);
+    if (he == hipSuccess) he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, g_aux);
+    (void)hipEventRecord(ctx.psi_t0, g_aux);
+    if (he == hipSuccess)
+        he = launch_psi(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
+                        reinterpret_cast<const int32_t *>(db + o_jtab), g_aux);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(hb + o_flags, db + o_flags, 4 * (size_t)count, hipMemcpyDeviceToHost, g_aux);
+    (void)hipEventRecord(ctx.psi_done, g_aux);
+    if (he != hipSuccess) {
+        msg = std::string("HIP error: ") + hipGetErrorString(he);
+        return CR_EDEVICE;
+    }
+    ctx.psi_dev = reinterpret_cast<uint64_t *>(db + o_psi);
+    ctx.psi_flags = reinterpret_cast<const int32_t *>(hb + o_flags);
     return CR_OK;
 }
 
@@ -1192,6 +1266,29 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     std::vector<std::string> errs(count);
     cr_status fatal = CR_OK;
     std::string fatal_msg;
+    auto drop_psi = [&]() {
+        if (ctx.psi_t0) (void)hipEventDestroy(ctx.psi_t0);
+        if (ctx.psi_done) (void)hipEventDestroy(ctx.psi_done);
+        ctx.psi_t0 = ctx.psi_done = nullptr;
+    };
+    // the call's psi launch only if some item can pass the setup (a prime in
+    // range, coefficients reduced mod p): invalid input is reported as such
+    bool any_valid = false;
+    for (int g = 0; g < count && !any_valid; g++) {
+        const int p = primes[g];
+        bool ok = p >= 7 && p < 50;
+        for (int t = 2; t * t <= p && ok; t++) ok = p % t != 0;
+        for (int k = 0; k < ctx.nco && ok; k++) ok = coeffs[(size_t)g * ctx.nco + k] < (uint32_t)p;
+        any_valid = ok;
+    }
+    if (ctx.device_psi && any_valid) {
+        fatal = start_psi_all(ctx, count, fatal_msg);
+        if (fatal != CR_OK) {
+            if (g_aux) (void)hipStreamSynchronize(g_aux);
+            drop_psi();
+            return fail(fatal, fatal_msg);
+        }
+    }
     auto stop_all = [&](int upto) {  // drain the device before reporting a failure
         (void)hipStreamSynchronize(ctx.stream);
         if (g_aux) (void)hipStreamSynchronize(g_aux);
@@ -1208,8 +1305,12 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         fatal = complete_sub(ctx, sub[k], st, errs, fatal_msg);
     if (fatal != CR_OK) {
         stop_all(S - 1);
+        drop_psi();
         return fail(fatal, fatal_msg);
     }
+    float psi_all_ms = 0;
+    if (ctx.psi_t0 && ctx.psi_done) (void)hipEventElapsedTime(&psi_all_ms, ctx.psi_t0, ctx.psi_done);
+    drop_psi();
     cr_status first = CR_OK;
     for (int i = 0; i < count; i++) {
         if (item_status) item_status[i] = st[i];
@@ -1249,6 +1350,8 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             }
         }
         if (stats->engine < 0) stats->engine = 0;
+        stats->psi_ms += psi_all_ms;
+        stats->device_ms += psi_all_ms;
     }
     return first;
 }

@@ -39,7 +39,7 @@ struct DevItem {
     const int32_t *frow;   // nfin: its coefficient row in coef
     uint64_t *Y;           // b x b output (coordinates, mod q)
     uint64_t *H;           // F x b scratch: summed pole-n numerators
-    const uint64_t *J;     // T x nsrc matrix of J_S mod q (input of k_psi)
+    const uint32_t *fcoef; // coefficients of f (input of k_psi, which builds J_S from them)
     uint64_t *psi_out;     // the psi buffer above, written by k_psi
     int32_t *flag;         // set by k_psi when J_S has no unit pivot in some row
 };

@@ -167,6 +167,23 @@ bool Family::init(int nvars, int degree, uint32_t s_mask, std::string &err) {
             for (int i = 0; i < nv; i++) e[i] = finU.at(U)[i] + g.at(k)[i] - (int)((smask >> i) & 1u);
             finmap[(size_t)U * s + k] = (int16_t)fin.rank(e);
         }
+    jtab.assign((size_t)tgt.count * nsrc, -1);
+    for (int t = 0; t < tgt.count; t++)
+        for (int i = 0; i < nv; i++) {
+            const bool inS = (smask >> i) & 1u;
+            for (int a = 0; a < srcblk[i].count; a++) {
+                bool ok = true;
+                for (int j = 0; j < nv; j++) {
+                    e[j] = tgt.at(t)[j] - srcblk[i].at(a)[j];
+                    ok = ok && e[j] >= 0;
+                }
+                if (!ok) continue;
+                const int w = inS ? e[i] + 1 : e[i];
+                if (inS) e[i] += 1;
+                const int idx = coeff.rank(e);
+                if (w > 0 && idx >= 0) jtab[(size_t)t * nsrc + srcoff[i] + a] = (idx << 8) | w;
+            }
+        }
     return true;
 }
 
@@ -541,11 +558,9 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         out.mq.init((u64)q);
     }
     const ModQ &mq = out.mq;
-    // psi = right inverse of J_S over Z/q (Proposition 3.3 decomposition)
-    if (!host_psi) {
-        out.J.resize(J.size());
-        for (size_t k = 0; k < J.size(); k++) out.J[k] = mq.from_int(J[k]);
-    } else {
+    // psi = right inverse of J_S over Z/q (Proposition 3.3 decomposition); on
+    // the device path k_psi builds J_S from the coefficients itself
+    if (host_psi) {
         std::vector<u64> Jq(J.size());
         for (size_t k = 0; k < J.size(); k++) Jq[k] = mq.from_int(J[k]);
         std::vector<u64> X;

@@ -82,6 +82,12 @@ struct Family {
     // final exponents U (|U| = |S| - 1) and finmap[Uidx*s + k] = fin rank of U + g_k - 1_S or -1
     MonoSpace finU;
     std::vector<int16_t> finmap;
+    // J_S from the coefficients of f: entry (t, srcoff[i] + a) is the
+    // coefficient c_e of f times w, jtab = (e << 8) | w, or -1 when it is 0
+    // (x^beta, beta = tgt_t - srcblk_i[a], is a monomial of d_i f (i in S:
+    // e = rank(beta + e_i), w = beta_i + 1) or of x_i d_i f (e = rank(beta),
+    // w = beta_i))
+    std::vector<int32_t> jtab;  // tgt.count x nsrc
     bool init(int nvars, int degree, uint32_t s_mask, std::string &err);
 };
 
@@ -92,7 +98,6 @@ struct ItemSetup {
     std::vector<int> hodge;          // |B_m|, m = 1..n (index m-1)
     std::vector<int> col_pole;       // b
     std::vector<u64> psi;            // nsrc x T, right inverse of J_S mod q (host_psi)
-    std::vector<u64> J;              // T x nsrc, J_S mod q (when psi is left to the device)
     std::vector<u64> rho;            // b x F, Griffiths-Dwork coordinates of pole-n numerators
     // start blocks (one chain each), sorted by pole descending
     std::vector<int16_t> chain_u;    // nchain x nv

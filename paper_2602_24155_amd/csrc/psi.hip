@@ -1,5 +1,6 @@
 // Right inverse psi of J_S mod q = p^M on the device, and its int8 digits
-// for the MFMA reduction kernel (gfx950).
+// for the MFMA reduction kernel (gfx950).  One launch covers every
+// hypersurface of a call: it needs only the coefficients of f.
 //
 // psi is the decomposition map of Proposition 3.3: for a numerator h in the
 // target of J_S, psi h gives the g_i with h = sum_{i in S} g_i d_i f +
@@ -70,9 +71,14 @@ constexpr int kPsiWaves = kPsiThreads / 64;
 // pivot inverse (u64), the pivot marks of the columns (C int), 8 int of scratch
 size_t psi_lds_bytes(int R, int C) { return (size_t)R * (C + R) * 8 + (size_t)(R + 1) * 8 + (size_t)C * 4 + 32; }
 
-__global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__ items, int R, int C) {
+// J_S is built in LDS from the coefficients of f and the family table jtab:
+// entry (r, k) = c_e * w for jtab[r C + k] = (e << 8) | w, or 0 for -1.  An
+// item with q = 0 (rejected on the host) is skipped.
+__global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__ items, int R, int C,
+                                                     const int32_t *__restrict__ jtab) {
     extern __shared__ __align__(16) unsigned char lds[];
     const DevItem it = items[blockIdx.x];
+    if (it.q == 0) return;  // uniform over the workgroup
     const PMod md{it.q, it.mu, it.sbits};
     const uint32_t p = (uint32_t)it.p, two32p = (uint32_t)((1ull << 32) % p);
     const int W = C + R, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -83,7 +89,12 @@ __global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__
     int *sh = used + C;  // sh[0]: pivot column, sh[1]: failure
     for (int r = wave; r < R; r += kPsiWaves)
         for (int k = lane; k < W; k += 64)
-            a[(size_t)r * W + k] = k < C ? it.J[(size_t)r * C + k] : (uint64_t)(k - C == r);
+            if (k < C) {
+                const int32_t e = jtab[(size_t)r * C + k];
+                a[(size_t)r * W + k] = e < 0 ? 0 : md.reduce((u128p)it.fcoef[e >> 8] * (uint32_t)(e & 255));
+            } else {
+                a[(size_t)r * W + k] = (uint64_t)(k - C == r);
+            }
     for (int k = tid; k < C; k += kPsiThreads) used[k] = 0;
     if (tid == 0) sh[1] = 0;
     __syncthreads();
@@ -167,12 +178,12 @@ __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ it
     }
 }
 
-hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, hipStream_t stream) {
+hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream) {
     if (nitems == 0) return hipSuccess;
     const size_t lds = psi_lds_bytes(R, C);
     hipError_t e = hipFuncSetAttribute((const void *)k_psi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_psi, dim3(nitems), dim3(kPsiThreads), lds, stream, items, R, C);
+    hipLaunchKernelGGL(k_psi, dim3(nitems), dim3(kPsiThreads), lds, stream, items, R, C, jtab);
     return hipGetLastError();
 }
 
