@@ -123,3 +123,24 @@ def test_full_size_engines_agree():
         assert res["stats"].engine == e
         assert np.array_equal(res["scaled"], runs[0]["scaled"])
         assert res["lpoly"] == runs[0]["lpoly"]
+
+
+def test_release_regrow_and_invalid_items():
+    """The device buffers (sub-batch arenas, the call's psi buffer) are freed by
+    cr_release and grow again; items the setup rejects (p not prime, a
+    coefficient not reduced mod p) sit beside valid ones, whose results
+    are unchanged."""
+    small = workload_items("quintic_curves_mixed", range(3))
+    a = run_batch(3, 5, small)
+    C.cr_release()
+    big = workload_items("quintic_curves_mixed", range(40))
+    b = run_batch(3, 5, big)
+    for i in range(3):
+        assert np.array_equal(a["scaled"][i], b["scaled"][i]) and a["lpoly"][i] == b["lpoly"][i]
+    bad = [(9, [1] * 21), (small[0][0], [small[0][0]] + [0] * 20)]
+    items = [small[0], bad[0], small[1], bad[1], small[2]]
+    res = C.cr_frobenius_batch(C.family(3, 5), [p for p, _ in items], [c for _, c in items], raise_on_error=False)
+    st = list(res["item_status"])
+    assert st[0] == st[2] == st[4] == C.CR_OK and st[1] != C.CR_OK and st[3] != C.CR_OK
+    for i, j in ((0, 0), (2, 1), (4, 2)):
+        assert np.array_equal(res["scaled"][i], a["scaled"][j]) and res["lpoly"][i] == a["lpoly"][j]
