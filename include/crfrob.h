@@ -129,7 +129,7 @@ typedef struct {
     int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a
                                 plain policy's and were reduced with the cheaper plain plan */
     int64_t reduce_launches; /* launches of the reduction kernels (sub-batches x phases x digit groups) */
-    double psi_ms;           /* device time of the right inverse of J_S and its digit packing */
+    double psi_ms;           /* device time of the right inverses of J_S (one launch per call, every item) */
 } cr_stats;
 
 /* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},
