@@ -48,7 +48,7 @@ hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, 
 size_t psi_lds_bytes(int R, int C);
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream);
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
-                           int nrt, int nkb, int T, int nsrc, hipStream_t stream);
+                           int nrt, int nkb, int T, int nsrc, int fold, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
 }  // namespace crf
 
@@ -534,7 +534,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
     if (sb.use_mfma && !sb.use_bins && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
-    sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs;
+    sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;  // folded psi digits
     for (int li = 0; li < nlive && sb.use_pairs; li++)
         if (!mfma5_supports(df, sb.dps[sb.live[li]].D)) sb.use_pairs = false;
     if (sb.use_mfma && !sb.use_bins && ctx.device_psi) sb.use_mfma = false;  // device packing follows the bin layout
@@ -846,7 +846,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         if (he == hipSuccess && sb.use_mfma)
             he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
                                  reinterpret_cast<const int16_t *>(db + sb.o_tables + ctx.fe->off_slot_src), ctx.nrt,
-                                 ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, g_aux);
+                                 ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, sb.use_pairs ? 1 : 0, g_aux);
         (void)hipEventRecord(sb.epe, g_aux);
         if (he == hipSuccess) he = hipStreamWaitEvent(stream, sb.epe, 0);
     } else {

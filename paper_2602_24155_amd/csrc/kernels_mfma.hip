@@ -443,6 +443,39 @@ __device__ __forceinline__ static void put_digits(int8_t *xp, double x, double Q
     }
 }
 
+// put_digits with the digit stride given at run time (one plane, or R2 bytes
+// for a column of the folded last K-block)
+template <int D>
+__device__ __forceinline__ static void put_digits_st(int8_t *xp, int stride, double x, double Qd, double bias,
+                                                     double Bsplit, double invBsplit, uint32_t magic, int shift,
+                                                     int Bi, int halfB) {
+    constexpr int DS = (D + 1) / 2;
+    double xs = x + bias;
+    if (xs >= Qd) xs -= Qd;
+    double xh = floor(xs * invBsplit);
+    double rl = fma(-xh, Bsplit, xs);
+    if (rl < 0.0) {
+        rl += Bsplit;
+        xh -= 1.0;
+    } else if (rl >= Bsplit) {
+        rl -= Bsplit;
+        xh += 1.0;
+    }
+    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
+#pragma unroll
+    for (int jd = 0; jd < DS; jd++) {
+        const uint32_t qd = __umulhi(vl, magic) >> shift;
+        xp[jd * stride] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
+        vl = qd;
+    }
+#pragma unroll
+    for (int jd = DS; jd < D; jd++) {
+        const uint32_t qd = __umulhi(vh, magic) >> shift;
+        xp[jd * stride] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
+        vh = qd;
+    }
+}
+
 // One tile (up to 32 vectors of one item) of the register-gather kernel.
 // colmapL / dirsL hold the family tables and sl this lane's bin slots.
 // One tile (up to 32 vectors of one item) of the register-gather kernel.
@@ -862,8 +895,9 @@ __device__ static void mfma5_init(const DevFamily &fam, const DevTile &tile, con
                 atomicOr(err, 2);
                 continue;
             }
-            put_digits<D, XS>(X + c * XS + col, (double)x, Qd, bias, Bsplit, invBsplit, it.magic, it.shift, it.B,
-                              it.halfB);
+            const int stride = col >= 32 * (NKB - 1) ? fam.T - 32 * (NKB - 1) : kCT * XS;  // folded last block
+            put_digits_st<D>(X + c * XS + col, stride, (double)x, Qd, bias, Bsplit, invBsplit, it.magic, it.shift,
+                             it.B, it.halfB);
         }
     }
 }
@@ -939,7 +973,7 @@ __device__ __forceinline__ static void mfma5_products(const v4i (&A)[D][NKB], co
 #pragma unroll
         for (int i = 0; i + j < D; i++)
 #pragma unroll
-            for (int kb = 0; kb < NKB; kb++)
+            for (int kb = 0; kb < (j == 0 ? NKB : NKB - 1); kb++)  // the last block is folded into plane 0
                 acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[kb], acc[i + j], 0, 0, 0);
     }
 }
@@ -957,7 +991,9 @@ struct FinState {
     double zd;       // z_k (wider sums)
     double carry;
     int nz;          // OR of the digits: the balanced digits of 0 mod Q' are all 0
-    int8_t *dst;
+    int8_t *dst;     // where the next digit goes
+    int stride;      // to the next digit: one plane, or R2 bytes for a folded column
+    int r2;          // target rows in the folded last K-block
     bool chk;        // continuing chain whose output has no column under its direction
 };
 
@@ -992,6 +1028,7 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         const bool put = cont && rv && col >= 0;
         const bool park = ends && rv;
         fs.dst = row + (put ? col : (park ? r : K));
+        fs.stride = (put && col >= 32 * (NKB - 1)) ? fs.r2 : kCT * XS;
         fs.carry = 0.0;
         fs.nz = 0;
         fs.chk = cont && rv && col < 0;
@@ -1030,7 +1067,8 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         fs.carry = q;
         const int di = (int)dk;
         fs.nz |= di;
-        fs.dst[k * kCT * XS] = (int8_t)di;
+        *fs.dst = (int8_t)di;
+        fs.dst += fs.stride;
         if constexpr (k == D - 1) bad |= (fs.chk && fs.nz != 0) ? 2 : 0;
     }
 }
@@ -1048,17 +1086,26 @@ __device__ __forceinline__ static void mfma5_pieces(const v16i (&acc)[D], const 
 // The products of a phase as a list of units, one MFMA each: plane J
 // (products with digit J of the chains' vectors) holds the units (kb, i),
 // kb major, so consecutive MFMAs feed different accumulators.
+//
+// The last K-block holds only the R2 = T - 32 (NKB - 1) target rows past the
+// full blocks: they are stored folded, digit J of row 32 (NKB - 1) + t at
+// byte 32 (NKB - 1) + R2 J + t of plane 0's row (R2 D <= 32), and the psi
+// fragments of that block are A'_m[:, R2 J + t] = digit m - J of psi[:, 32
+// (NKB - 1) + t] (J <= m).  One product A'_m x (plane 0's last block) then
+// gives the whole last-block contribution to accumulator m, so planes J >= 1
+// have no last-block units.
 template <int D, int NKB>
 struct UnitMap {
-    static constexpr int count = D * (D + 1) / 2 * NKB;
+    static constexpr int blocks(int J) { return J == 0 ? NKB : NKB - 1; }
+    static constexpr int count = D * NKB + D * (D - 1) / 2 * (NKB - 1);
     static constexpr int plane(int u) {
         int J = 0;
-        while (u >= (D - J) * NKB) u -= (D - J) * NKB, J++;
+        while (u >= (D - J) * blocks(J)) u -= (D - J) * blocks(J), J++;
         return J;
     }
     static constexpr int first(int J) {  // first unit of plane J
         int t = 0;
-        for (int q = 0; q < J; q++) t += (D - q) * NKB;
+        for (int q = 0; q < J; q++) t += (D - q) * blocks(q);
         return t;
     }
     // The operands of plane J (J >= 1) are read from LDS kLead units before
@@ -1097,7 +1144,7 @@ __device__ __forceinline__ static void mfma5_unit(const v4i (&A)[D][NKB], const 
         constexpr int JL = UM::plane_loaded_at(U);
         if constexpr (JL > 0) {
 #pragma unroll
-            for (int b = 0; b < NKB; b++)
+            for (int b = 0; b < NKB - 1; b++)
                 xb[JL & 1][b] = *reinterpret_cast<const v4i *>(Xp + (JL * kCT + c) * XS + b * 32 + half * 16);
         }
         accP[i + J] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i][kb], xb[J & 1][kb], accP[i + J], 0, 0, 0);
@@ -1125,7 +1172,7 @@ template <int NRT, int NKB, int D, int NV, bool Z32>
 __device__ __forceinline__ static void mfma5_phase(const v4i (&A)[D][NKB], const int8_t *Xp, int c, int half,
                                                    v16i (&accP)[D], const v16i (&accF)[D], const uint32_t (&sl)[16],
                                                    const TileState<NV> &tsF, const int16_t *cm, int8_t *rowF,
-                                                   const DevDigitItem &it, int8_t *Xz, int tid, int &bad) {
+                                                   const DevDigitItem &it, int8_t *Xz, int tid, int r2, int &bad) {
     constexpr int XS = NKB * 32 + 16;
     constexpr int G = slot_groups(NRT);
     static_assert(G <= 9, "slot groups");
@@ -1141,6 +1188,7 @@ __device__ __forceinline__ static void mfma5_phase(const v4i (&A)[D][NKB], const
 #pragma unroll
     for (int k = 0; k < D; k++) accP[k] = v16i{0};
     FinState fs;
+    fs.r2 = r2;
     mfma5_unit<NRT, NKB, D, NV, Z32, 0>(A, Xp, c, half, xb, accP, accF, sl, tsF, cols, rowF, it, fs,
                                         reinterpret_cast<v4i *>(Xz), tid, bad);
 }
@@ -1222,11 +1270,12 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
     v16i accA[D], accB[D];
     mfma5_products<NKB, D>(A, XA, c, half, accA);
     const int steps = max(tA.steps, tB.steps);
+    const int r2 = fam.T - 32 * (NKB - 1);  // target rows in the folded last K-block
     for (int step = 0; step < steps; step++) {
         // phase 1: products of B || finish of A
         mfma5_book<NV>(fam, sA, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XBp + cb * XB, c, half, accB, accA, sl, sA, colmapL + sA.dirn * s,
-                                          XA + (ca ^ 1) * XB + c * XS, it, XA + ca * XB, tid, bad);
+                                          XA + (ca ^ 1) * XB + c * XS, it, XA + ca * XB, tid, r2, bad);
         __syncthreads();
         mfma5_flush<NRT, NKB, D, NV>(fam, sA, XA + (ca ^ 1) * XB, c, bin, tA.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sA);
@@ -1234,7 +1283,7 @@ __device__ static void mfma5_pair(const DevFamily &fam, const DevTile *tp, const
         // phase 2: products of A (next step) || finish of B
         mfma5_book<NV>(fam, sB, bad);
         mfma5_phase<NRT, NKB, D, NV, Z32>(A, XA + ca * XB, c, half, accA, accB, sl, sB, colmapL + sB.dirn * s,
-                                          XBp + (cb ^ 1) * XB + c * XS, it, XBp + cb * XB, tid, bad);
+                                          XBp + (cb ^ 1) * XB + c * XS, it, XBp + cb * XB, tid, r2, bad);
         __syncthreads();
         mfma5_flush<NRT, NKB, D, NV>(fam, sB, XBp + (cb ^ 1) * XB, c, bin, tB.chain0, it, store, hbuf, bad);
         mfma5_advance<NV>(sB);
@@ -1384,6 +1433,10 @@ bool mfma5_supports(const DevFamily &fam, int D) {
     int nrt, nkb;
     if (!mfma4_supports(fam, D)) return false;
     mfma4_shape(fam, nrt, nkb);
+    // the last K-block is folded: its R2 target rows times D digits fit one block
+    const int r2 = fam.T - 32 * (nkb - 1);
+    if (r2 < 1 || r2 * D > 32) return false;
+    if (fam.s > 32 * (nkb - 1)) return false;  // parked digits stay below the folded block
     // the digits of an ending chain are parked at columns r < s of its rows
     if (fam.s > nkb * 32) return false;
     return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));

@@ -150,10 +150,14 @@ __global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__
 // source rows placed by the bin layout:
 // apack[(((rt*D + i)*nkb + kb)*64 + lane)*16 + jj] = digit i of
 // psi[slot_src(2 rt + (lane%32 >> 2 & 1), (lane%32 >> 3) * 4 + lane%4)][32 kb + (lane/32)*16 + jj].
+// With fold set (tile-pair kernel), the last K-block holds A'_i instead: its
+// k-slot R2 J + t (R2 = T - 32 (nkb - 1) rows) carries digit i - J of
+// psi[row][32 (nkb - 1) + t] for J <= i, 0 otherwise; the reduction kernel
+// stores digit J of those target rows at the same k-slot of plane 0.
 __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ items,
                                                   const DevDigitItem *__restrict__ ditems,
                                                   const int16_t *__restrict__ slot_src, int nrt, int nkb, int T,
-                                                  int nsrc) {
+                                                  int nsrc, int fold) {
     const DevItem it = items[blockIdx.y];
     const DevDigitItem dd = ditems[blockIdx.y];
     const int D = dd.D;
@@ -164,18 +168,26 @@ __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ it
     const int kb = rest % nkb, rt = rest / nkb;
     const int rho = lane & 31, hh = (rho >> 2) & 1, js = (rho >> 3) * 4 + (rho & 3);
     const int row = slot_src[(2 * rt + hh) * 16 + js];
-    const int k = 32 * kb + (lane >> 5) * 16 + jj;
-    uint64_t x = (row >= 0 && row < nsrc && k < T) ? it.psi_out[(size_t)row * T + k] : 0;
+    const int kslot = (lane >> 5) * 16 + jj;
+    const bool folded = fold && kb == nkb - 1;
+    const int base = 32 * (nkb - 1), r2 = T - base;
+    const int Jf = folded ? kslot / r2 : 0;  // plane whose folded rows this k-slot carries
+    const int k = folded ? base + kslot % r2 : 32 * kb + kslot;
+    const bool inside = row >= 0 && row < nsrc && k < T && (!folded || Jf < D);
+    uint64_t x = inside ? it.psi_out[(size_t)row * T + k] : 0;
     // balanced digits of x = unsigned digits of (x + (Q'-1)/2) mod Q', minus (B-1)/2
     const uint64_t Q = dd.Qp, bias = (Q - 1) / 2, B = (uint64_t)dd.B;
     x += bias;
     if (x >= Q) x -= Q;
     int8_t *out = dd.apack_out + ((size_t)(rt * D) * nkb + kb) * 1024 + (size_t)lane * 16 + jj;
+    int8_t dig[16];
     for (int i = 0; i < D; i++) {
         const uint64_t qd = x / B;
-        out[(size_t)i * nkb * 1024] = (int8_t)((int)(x - qd * B) - dd.halfB);
+        dig[i] = (int8_t)((int)(x - qd * B) - dd.halfB);
         x = qd;
     }
+    // unfolded: fragment i holds digit i; folded: fragment i holds digit i - Jf
+    for (int i = 0; i < D; i++) out[(size_t)i * nkb * 1024] = !folded ? dig[i] : (inside && Jf <= i ? dig[i - Jf] : 0);
 }
 
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream) {
@@ -188,11 +200,11 @@ hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int3
 }
 
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
-                           int nrt, int nkb, int T, int nsrc, hipStream_t stream) {
+                           int nrt, int nkb, int T, int nsrc, int fold, hipStream_t stream) {
     if (nitems == 0) return hipSuccess;
     const int n = nrt * nkb * 64 * 16;
     hipLaunchKernelGGL(k_pack_psi, dim3((n + 255) / 256, nitems), dim3(256), 0, stream, items, ditems, slot_src, nrt,
-                       nkb, T, nsrc);
+                       nkb, T, nsrc, fold);
     return hipGetLastError();
 }
 
