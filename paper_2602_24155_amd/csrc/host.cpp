@@ -1052,7 +1052,6 @@ static u64 ipow(u64 p, int e) {
 cr_status finish_item(const Family &fam, const ItemSetup &it, const u64 *Y, u64 *frob, int32_t *col_pole,
                       int32_t *col_prec, int64_t *lpoly, std::string &err) {
     const int b = it.b, p = it.p, n = fam.n, w = n - 1;
-    const ModQ &mq = it.mq;
     std::vector<u64> phi((size_t)b * b);
     for (int c = 0; c < b; c++) {
         const u64 div = ipow(p, it.col_shift[c]);

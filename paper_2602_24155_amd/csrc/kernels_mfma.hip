@@ -786,49 +786,13 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t stream) {
 // straight-line block closed by one barrier:
 //   phase 1: products of tile B (step t)   || finish of tile A (step t)
 //   phase 2: products of tile A (step t+1) || finish of tile B (step t)
-// The finish of a tile (weighted gather, exact recombination, digit split)
-// is branch-free: the new digits come from a carry propagation over the
-// digit-position sums (no recombination), a digit that has nowhere to go is
+// The finish of a tile (weighted gather, digit split) is branch-free: the new
+// digits come from a carry propagation over the digit-position sums (no
+// recombination), a digit that has nowhere to go is
 // written to the pad column of its plane row (never read by the products),
 // and the digits of a chain that ends at this step are parked at column r of
 // its own rows of the next planes (which no later step of that chain reads),
 // then turned into residues and written out after the barrier.
-// Branch-free forms of mod_fp and put_digits (the corrections are added as
-// multiples of the flag), so that a whole finishing block is one basic block.
-__device__ __forceinline__ double mod_fp_nb(double x, double Q, double invQ) {
-    const double qt = floor(x * invQ);
-    double r = fma(-qt, Q, x);
-    r += Q * (double)(r < 0.0);
-    r -= Q * (double)(r >= Q);
-    return r;
-}
-
-template <int D, int XS>
-__device__ __forceinline__ static void put_digits_nb(int8_t *xp, double x, double Qd, double bias, double Bsplit,
-                                                     double invBsplit, uint32_t magic, int shift, int Bi, int halfB) {
-    constexpr int DS = (D + 1) / 2;
-    double xs = x + bias;
-    xs -= Qd * (double)(xs >= Qd);
-    double xh = floor(xs * invBsplit);
-    double rl = fma(-xh, Bsplit, xs);
-    const double lowf = (double)(rl < 0.0), highf = (double)(rl >= Bsplit);
-    rl += Bsplit * (lowf - highf);
-    xh += highf - lowf;
-    uint32_t vl = (uint32_t)rl, vh = (uint32_t)xh;
-#pragma unroll
-    for (int jd = 0; jd < DS; jd++) {
-        const uint32_t qd = __umulhi(vl, magic) >> shift;
-        xp[jd * kCT * XS] = (int8_t)((int)(vl - qd * (uint32_t)Bi) - halfB);
-        vl = qd;
-    }
-#pragma unroll
-    for (int jd = DS; jd < D; jd++) {
-        const uint32_t qd = __umulhi(vh, magic) >> shift;
-        xp[jd * kCT * XS] = (int8_t)((int)(vh - qd * (uint32_t)Bi) - halfB);
-        vh = qd;
-    }
-}
-
 template <int NV>
 struct TileState {
     int U[NV], V[NV];
