@@ -1,4 +1,4 @@
-"""Random quartic K3 surfaces (config 3): stored oracle results.
+"""Random quartic K3 surfaces over F_7, F_11 and F_13: stored oracle results.
 
 tests/golden/k3_golden.json is written by tests/golden/make_k3_golden.py,
 which calls only oracle/ (about a minute per surface).  On the CPU the stored
