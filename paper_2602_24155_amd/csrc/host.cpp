@@ -844,7 +844,9 @@ bool digit_params(int p, int M, int T, int nv, u64 wtmax, int dmax, DigitParams 
     dp.h = h;
     dp.ds = ds;
     dp.halfB = (int)half;
-    dp.z32 = Zmax < std::ldexp(1.0L, 31) ? 1 : 0;
+    // Z32: the weighted sums z_k and the carry sums t_k = z_k + c_k fit int32
+    // (|c_(k+1)| <= |t_k| / B + 1/2, so |t_k| <= (Zmax + 1/2) B / (B - 1))
+    dp.z32 = (Zmax + 0.5L) * (long double)B / (long double)(B - 1) < std::ldexp(1.0L, 31) - 1 ? 1 : 0;
     dp.shift = ell;
     dp.magic = (uint32_t)(((1ULL << (32 + ell)) / (unsigned long long)B) + 1);
     dp.Qp = (u64)Q;

@@ -953,7 +953,8 @@ struct FinState {
     int wt[3];
     int zi;          // z_k (32-bit sums)
     double zd;       // z_k (wider sums)
-    double carry;
+    double carry;    // carry into position k (wider sums)
+    int ci;          // carry into position k (32-bit sums)
     int nz;          // OR of the digits: the balanced digits of 0 mod Q' are all 0
     int8_t *dst;     // where the next digit goes
     int stride;      // to the next digit: one plane, or R2 bytes for a folded column
@@ -994,6 +995,7 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         fs.dst = row + (put ? col : (park ? r : K));
         fs.stride = (put && col >= 32 * (NKB - 1)) ? fs.r2 : kCT * XS;
         fs.carry = 0.0;
+        fs.ci = 0;
         fs.nz = 0;
         fs.chk = cont && rv && col < 0;
     } else if constexpr (w % 2 == 1) {  // gather of position k
@@ -1013,25 +1015,41 @@ __device__ __forceinline__ static void mfma5_piece(const v16i (&acc)[D], const u
         constexpr int k = (w - 2) / 2;
         // t = z_k + carry, carry = round(t / B), d_k = t - B carry (|d_k| <=
         // (B-1)/2 since B is odd); the carry out of position D - 1 is a
-        // multiple of Q' and is dropped.  round() adds and subtracts 1.5 2^52;
-        // for |t| < 2^32 (Z32) its error (< 2^-23) cannot carry t / B across a
-        // half-integer (t / B lies at least 1 / (2B) from one), so it is exact;
-        // for wider sums a range test fixes the one-unit error it can make.
-        const double t = (Z32 ? (double)fs.zi : fs.zd) + fs.carry;
+        // multiple of Q' and is dropped.  round() adds 1.5 2^52: the sum then
+        // lies in [2^52, 2^53), where the unit in the last place is 1, so its
+        // mantissa is 2^51 + round(t / B).  For |t| < 2^31 (Z32: the host
+        // bounds the carry sums too) the error of the product (< 2^-23) cannot
+        // carry t / B across a half-integer (t / B lies at least 1 / (2B) from
+        // one), so the rounding is exact; the carry is then the low word of
+        // the sum (two's complement, as 2^51 is 0 mod 2^32), and the digit is
+        // only needed mod 2^8 (|d_k| < 128), where a 24-bit multiply-add gives
+        // it.  For wider sums the carry stays in fp64 and a range test fixes
+        // the one-unit error the rounding can make.
         const double Bd = it.Bd, invB = 1.0 / Bd;
         constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
-        double q = fma(t, invB, kRound) - kRound;
-        double dk = fma(-q, Bd, t);
-        if constexpr (!Z32) {
+        if constexpr (Z32) {
+            const int t = fs.zi + fs.ci;
+            fs.ci = __double2loint(fma((double)t, invB, kRound));
+            // low 24 bits of the carry times 2^24 - B, plus t: = d_k mod 2^8.
+            // Written out because, with only 8 result bits in use, the
+            // compiler would otherwise narrow it to a quarter-rate 32-bit mul.
+            unsigned du;
+            asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(du) : "v"(fs.ci), "v"((1u << 24) - (unsigned)it.B), "v"(t));
+            fs.nz |= (int)(du & 0xffu);
+            *fs.dst = (int8_t)du;
+        } else {
+            const double t = fs.zd + fs.carry;
+            double q = fma(t, invB, kRound) - kRound;
+            double dk = fma(-q, Bd, t);
             const double hB = (double)it.halfB;
             const double up1 = (double)(dk > hB), dn1 = (double)(dk < -hB);
             q += up1 - dn1;
             dk += Bd * (dn1 - up1);
+            fs.carry = q;
+            const int di = (int)dk;
+            fs.nz |= di;
+            *fs.dst = (int8_t)di;
         }
-        fs.carry = q;
-        const int di = (int)dk;
-        fs.nz |= di;
-        *fs.dst = (int8_t)di;
         fs.dst += fs.stride;
         if constexpr (k == D - 1) bad |= (fs.chk && fs.nz != 0) ? 2 : 0;
     }
