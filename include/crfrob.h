@@ -189,7 +189,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
 cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs, cr_stats *stats);
 
 /*
- * Learned policy (the benchmark spec's extension; the paper's Section 4.4 asks
+ * Learned policy (an extension of the method: the paper's Section 4.4 asks
  * for better policies).  The network's inputs for a term at exponent u of a
  * p-chunk phase that ends at pole `stop`, and a direction v valid for all
  * k = pole - stop steps (u' = u - k v):
