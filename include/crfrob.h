@@ -106,6 +106,13 @@ typedef struct {
                          launch parameters repeat */
     cr_mlp *mlp;      /* model of CR_POLICY_LEARNED (required then, ignored otherwise); the
                          library uses its device scratch, so one model serves one call at a time */
+    int32_t M;        /* working precision override (Section 2.5: the modulus p^M of the
+                         reduction); 0 = the least M that keeps r digits in every column (header
+                         comment).  A smaller M is rejected (CR_EINVAL); a larger one computes
+                         more digits of every column (col_prec grows by the difference) */
+    int32_t n_series_m[6]; /* per pole order override of N_m (Proposition 2.1: the Frobenius
+                         series of a column of pole m is truncated after N_m terms), entry m-1
+                         for m = 1..n; 0 = n_series (or r + 1) */
 } cr_family;
 
 /* Per-call statistics (all counts are summed over the batch). */
@@ -133,20 +140,36 @@ typedef struct {
 } cr_stats;
 
 /* Sizes: ncoeff = C(d+n, n); s = C(dn, n) = dim Homog_{dn-n} (side of R_{u,v},
- * Proposition 3.3); b = dimension of H^n_dR(U) (side of Phi').  Pure function
- * of (nvars, degree); outputs may be NULL. */
+ * Proposition 3.3); b = dimension of H^n_dR(U) (side of Phi', the sum over
+ * m = 1..n of the basis sizes of Section 2.3).  Pure function of (nvars,
+ * degree); outputs may be NULL.  CR_EINVAL for unsupported nvars / degree. */
 cr_status cr_query_dims(int32_t nvars, int32_t degree, int32_t *ncoeff, int32_t *s, int32_t *b);
 
-/* Exponent vectors of the degree-d monomials in coefficient order:
- * exps[k * nvars + i] = exponent of x_i in monomial k.  Caller-owned, ncoeff*nvars. */
+/* Section 2.1 (the lift of f): the exponent vectors of the degree-d monomials
+ * in the order in which every entry point takes the coefficients of f,
+ * lexicographically descending: exps[k * nvars + i] = exponent of x_i in
+ * monomial k.  exps is caller-owned, ncoeff * nvars entries.  CR_EINVAL for a
+ * null pointer or unsupported nvars / degree. */
 cr_status cr_monomials(int32_t nvars, int32_t degree, int32_t *exps);
 
-/* Precision chosen for prime p (header comment): r, N (= N_m for every m) and
- * M.  Outputs may be NULL. */
+/* Section 2.5: precision chosen for prime p under fam's overrides (header
+ * comment): the relative precision r, the largest series order N_m over
+ * m = 1..n (all equal unless fam->n_series_m sets some) and the working
+ * precision M.  Outputs may be NULL.  CR_EINVAL if an override is out of
+ * range or fam->M is below the least working precision. */
 cr_status cr_precision(const cr_family *fam, int32_t p, int32_t *r, int32_t *n_series, int32_t *M);
 
-/* 1 in *smooth iff f mod p is smooth (and S-smooth for fam->s_mask); the
- * status is CR_OK either way for valid arguments. */
+/* Words per residue of the Frobenius outputs for prime p (Section 2.5: the
+ * coordinates are residues mod p^M): 1 when p^M < 2^55, the residues of this
+ * build.  Larger moduli are rejected here and by every computing entry point
+ * with CR_EPRECISION.  Host only. */
+cr_status cr_residue_words(const cr_family *fam, int32_t p, int32_t *words);
+
+/* Definition 3.1: *smooth = 1 iff f mod p is smooth (Jacobian criterion) and,
+ * for fam->s_mask != 0, S-smooth (J_S : (+)_{i in S} Homog_{D-d+1} (+)
+ * (+)_{i not in S} Homog_{D-d} -> Homog_D surjective mod p); 0 otherwise.  The
+ * status is CR_OK either way for valid arguments; CR_EINVAL for null
+ * pointers or a bad family, CR_ENOTPRIME / CR_EPRANGE for p.  Host only. */
 cr_status cr_check_smooth(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t *smooth);
 
 /*
@@ -180,6 +203,14 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
                              const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
                              int32_t *col_pole, int32_t *col_prec, int64_t *lpoly,
                              int32_t *item_status, cr_stats *stats, void *hip_stream);
+
+/* One hypersurface (the same path as cr_frobenius_batch with count = 1; its
+ * buffers are those of one batch item): Sections 2-4 for f with coefficients
+ * coeffs[ncoeff] at prime p.  frob[b * b], frob_scaled[b * b] (may be NULL),
+ * col_pole[b], col_prec[b], lpoly[(b + 1) * 4] as in cr_frobenius_batch.
+ * Returns the item's status. */
+cr_status cr_frobenius(const cr_family *fam, int32_t p, const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
+                       int32_t *col_pole, int32_t *col_prec, int64_t *lpoly, cr_stats *stats, void *hip_stream);
 
 /* Host-only planning of one hypersurface under fam->policy (no device work):
  * fills start_blocks, column_steps, chunks, vectors, merged_terms,
@@ -243,7 +274,8 @@ cr_status cr_mlp_train(cr_mlp *m, int32_t rows, const float *x, const float *t, 
 cr_status cr_trace_policy(const cr_family *fam, int32_t p, const uint32_t *coeffs, int32_t cap, float *x, float *t,
                           int32_t *rows);
 
-/* Autotuner: runs the batch under every (policy, launch) pair -- policies
+/* Autotuner of the batched launch (an extension of the method; the paper
+ * parallelises only across CPU threads, Sections 5.1 and 7): runs the batch under every (policy, launch) pair -- policies
  * depth-first, p-chunk, var-by-var (and learned when fam->mlp is set), launch
  * modes 0, 1, 2 -- once to warm up and `trials` times timed (wall clock of
  * whole cr_frobenius_batch calls), and returns the fastest in best_policy /

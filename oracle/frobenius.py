@@ -177,6 +177,9 @@ def frobenius(nv, d, p, coeffs, S=None, r=None, N=None, M=None, lpoly=True,
         mask = np.zeros(coef.shape[1], dtype=bool)
         mask[list(columns)] = True
         coef = coef * mask
+        # start terms whose coefficients in the kept columns are all zero add nothing
+        keep = [k for k in range(len(E)) if any(int(x) for x in coef[k])]
+        E, P, coef = [E[k] for k in keep], [P[k] for k in keep], coef[keep, :]
     H, steps = reduce_blocks(f, nv, d, p, S, q, E, P, coef, check_identity=check_identity)
     Y = gd_coordinates(f, nv, d, p, q, B, H.astype(object))
     b = len(col_pole)

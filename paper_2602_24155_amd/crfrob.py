@@ -16,8 +16,8 @@ CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
     CR_EPRECISION, CR_ENOMEM, CR_EDEVICE, CR_ESELFCHECK = range(10)
 CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
-EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
+EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_residue_words", "cr_check_smooth",
+           "cr_frobenius_batch", "cr_frobenius", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
            "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_autotune", "cr_release",
            "cr_last_error"]
 
@@ -25,7 +25,8 @@ EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_check_smooth",
 class cr_family(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
                 ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32),
-                ("engine", ctypes.c_int32), ("launch", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("engine", ctypes.c_int32), ("launch", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("M", ctypes.c_int32), ("n_series_m", ctypes.c_int32 * 6)]
 
 
 class cr_tuning(ctypes.Structure):
@@ -74,7 +75,10 @@ def lib():
         L.cr_query_dims.argtypes = [i32, i32, P(i32), P(i32), P(i32)]
         L.cr_monomials.argtypes = [i32, i32, P(i32)]
         L.cr_precision.argtypes = [P(cr_family), i32, P(i32), P(i32), P(i32)]
+        L.cr_residue_words.argtypes = [P(cr_family), i32, P(i32)]
         L.cr_check_smooth.argtypes = [P(cr_family), i32, P(u32), P(i32)]
+        L.cr_frobenius.argtypes = [P(cr_family), i32, P(u32), P(u64), P(u64), P(i32), P(i32), P(i64),
+                                   P(cr_stats), ctypes.c_void_p]
         L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
                                          P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
         L.cr_policy_cost.argtypes = [P(cr_family), i32, P(u32), P(cr_stats)]
@@ -112,9 +116,11 @@ LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
 
 
 def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO, mlp=None,
-           launch=LAUNCH_GRID):
+           launch=LAUNCH_GRID, M=0, n_series_m=None):
+    """n_series_m: series orders N_m of pole orders m = 1..n (0 entries = n_series)."""
+    nm = list(n_series_m or []) + [0] * (6 - len(n_series_m or []))
     return cr_family(nvars, degree, s_mask, policy, r, n_series, engine, launch,
-                     mlp.handle if mlp is not None else None)
+                     mlp.handle if mlp is not None else None, M, (ctypes.c_int32 * 6)(*nm))
 
 
 def cr_query_dims(nvars, degree):
@@ -134,6 +140,12 @@ def cr_precision(fam, p):
     r, N, M = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().cr_precision(ctypes.byref(fam), p, ctypes.byref(r), ctypes.byref(N), ctypes.byref(M)))
     return r.value, N.value, M.value
+
+
+def cr_residue_words(fam, p):
+    out = ctypes.c_int32()
+    _check(lib().cr_residue_words(ctypes.byref(fam), p, ctypes.byref(out)))
+    return out.value
 
 
 def cr_check_smooth(fam, p, coeffs):
@@ -182,6 +194,26 @@ def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise
         "status": st, "item_status": ist, "frob": frob, "scaled": scaled, "col_pole": pole,
         "col_prec": prec, "lpoly": [_lpoly_ints(lp[i]) for i in range(count)] if lpoly_ints else lp, "stats": stats,
     }
+
+
+def cr_frobenius(fam, p, coeffs, stream=None, want_scaled=True, raise_on_error=True):
+    """One hypersurface; the same dict as cr_frobenius_batch, without the batch axis."""
+    nco, _s, b = cr_query_dims(fam.nvars, fam.degree)
+    co = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint32).reshape(nco))
+    frob = np.zeros((b, b), dtype=np.uint64)
+    scaled = np.zeros((b, b), dtype=np.uint64) if want_scaled else None
+    pole = np.zeros(b, dtype=np.int32)
+    prec = np.zeros(b, dtype=np.int32)
+    lp = np.zeros((b + 1, 4), dtype=np.int64)
+    stats = cr_stats()
+    st = lib().cr_frobenius(ctypes.byref(fam), p, _ptr(co, ctypes.c_uint32), _ptr(frob, ctypes.c_uint64),
+                            _ptr(scaled, ctypes.c_uint64) if scaled is not None else None,
+                            _ptr(pole, ctypes.c_int32), _ptr(prec, ctypes.c_int32), _ptr(lp, ctypes.c_int64),
+                            ctypes.byref(stats), ctypes.c_void_p(stream or 0))
+    if raise_on_error:
+        _check(st)
+    return {"status": st, "frob": frob, "scaled": scaled, "col_pole": pole, "col_prec": prec,
+            "lpoly": _lpoly_ints(lp), "stats": stats}
 
 
 def cr_policy_cost(fam, p, coeffs):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <functional>
 #include <cstring>
@@ -494,8 +495,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     sb.digit_ok.assign(count, 0);
     parallel_for(count, [&](int i) {
         const int g = sb.idx[i];
-        sb.st[i] = setup_item(F, ctx.primes[g], ctx.coeffs + (size_t)g * ctx.nco, fam->r, fam->n_series,
-                              sb.items[i], sb.errs[i], false, !ctx.device_psi);
+        sb.st[i] = setup_item(F, ctx.primes[g], ctx.coeffs + (size_t)g * ctx.nco, PrecOpts::from(fam), sb.items[i],
+                              sb.errs[i], false, !ctx.device_psi);
         if (sb.st[i] == CR_OK && sb.items[i].b != b) {
             sb.st[i] = CR_ESELFCHECK;
             sb.errs[i] = "basis size differs from the Hodge numbers";
@@ -1035,7 +1036,7 @@ bool trace_item(const cr_family *fam, int p, const uint32_t *coeffs, std::vector
         return false;
     }
     ItemSetup it;
-    st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err);
+    st = setup_item(fe->fam, p, coeffs, PrecOpts::from(fam), it, err);
     if (st != CR_OK) return false;
     PChunkPlanner pc;
     if (!pc.init(fe->fam, it, CR_POLICY_P_CHUNK, err)) {
@@ -1085,11 +1086,25 @@ cr_status cr_precision(const cr_family *fam, int32_t p, int32_t *r, int32_t *n_s
     const int n = fam->nvars - 1;
     std::vector<int> hodge(n);
     for (int m = 1; m <= n; m++) hodge[m - 1] = (int)hodge_size(fam->nvars, fam->degree, m);
-    int rr, NN, MM;
-    if (!choose_precision(p, n, hodge, fam->r, fam->n_series, rr, NN, MM, err)) return fail(CR_EINVAL, err);
+    int rr, MM;
+    std::vector<int> Nm;
+    if (!choose_precision(p, n, hodge, PrecOpts::from(fam), rr, Nm, MM, err)) return fail(CR_EINVAL, err);
     if (r) *r = rr;
-    if (n_series) *n_series = NN;
+    if (n_series) *n_series = *std::max_element(Nm.begin(), Nm.end());
     if (M) *M = MM;
+    return CR_OK;
+}
+
+cr_status cr_residue_words(const cr_family *fam, int32_t p, int32_t *words) {
+    if (!words) return fail(CR_EINVAL, "null pointer");
+    int32_t r, N, M;
+    cr_status st = cr_precision(fam, p, &r, &N, &M);
+    if (st != CR_OK) return st;
+    if (p < 2) return fail(CR_ENOTPRIME, "p is not prime");
+    long double q = 1;
+    for (int k = 0; k < M; k++) q *= p;
+    if (q >= std::ldexp(1.0L, 55)) return fail(CR_EPRECISION, "p^M exceeds the 55-bit residues of this build");
+    *words = 1;
     return CR_OK;
 }
 
@@ -1103,7 +1118,7 @@ cr_status cr_check_smooth(const cr_family *fam, int32_t p, const uint32_t *coeff
     }
     if (!fe) return fail(CR_EINVAL, err);
     ItemSetup it;
-    cr_status st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err, true);
+    cr_status st = setup_item(fe->fam, p, coeffs, PrecOpts::from(fam), it, err, true);
     if (st == CR_ESINGULAR || st == CR_ENOT_S_SMOOTH) {
         *smooth = 0;
         return CR_OK;
@@ -1124,7 +1139,7 @@ cr_status cr_policy_cost(const cr_family *fam, int32_t p, const uint32_t *coeffs
     if (!fe) return fail(CR_EINVAL, err);
     auto t0 = std::chrono::steady_clock::now();
     ItemSetup it;
-    cr_status st = setup_item(fe->fam, p, coeffs, fam->r, fam->n_series, it, err);
+    cr_status st = setup_item(fe->fam, p, coeffs, PrecOpts::from(fam), it, err);
     if (st != CR_OK) return fail(st, err);
     ItemPlan plan;
     if (!plan_item(fe->fam, it, fam->policy, plan, err)) return fail(CR_EINVAL, err);
@@ -1190,10 +1205,11 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
             ModQ mq;
             bool prime = p >= 2;
             for (int t = 2; t * t <= p && prime; t++) prime = p % t != 0;
-            int rr, NN, MM;
+            int rr, MM;
+            std::vector<int> NN;
             std::string e2;
             if (prime && p >= 7 && p < 50 && p > n && F.d % p != 0 &&
-                choose_precision(p, n, hodge, ctx.fam->r, ctx.fam->n_series, rr, NN, MM, e2)) {
+                choose_precision(p, n, hodge, PrecOpts::from(ctx.fam), rr, NN, MM, e2)) {
                 u64 q = 1;
                 for (int k = 0; k < MM; k++) q *= (u64)p;
                 mq.init(q);
@@ -1354,6 +1370,15 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         stats->device_ms += psi_all_ms;
     }
     return first;
+}
+
+cr_status cr_frobenius(const cr_family *fam, int32_t p, const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
+                       int32_t *col_pole, int32_t *col_prec, int64_t *lpoly, cr_stats *stats, void *hip_stream) {
+    int32_t st_item = CR_OK;
+    const int32_t primes[1] = {p};
+    cr_status st = cr_frobenius_batch(fam, 1, primes, coeffs, frob, frob_scaled, col_pole, col_prec, lpoly, &st_item,
+                                      stats, hip_stream);
+    return st != CR_OK ? st : (cr_status)st_item;
 }
 
 cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,

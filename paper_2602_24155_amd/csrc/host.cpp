@@ -245,8 +245,17 @@ static bool exceeds(int p, int e, long long scale, int iw) {
 
 static long long binom_ll(int n, int k) { return binom(n, k); }
 
-bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_override, int n_override,
-                      int &r, int &N, int &M, std::string &err) {
+PrecOpts PrecOpts::from(const cr_family *fam) {
+    PrecOpts o;
+    o.r = fam->r;
+    o.N = fam->n_series;
+    for (int m = 0; m < kMaxVars; m++) o.Nm[m] = fam->n_series_m[m];
+    o.M = fam->M;
+    return o;
+}
+
+bool choose_precision(int p, int n, const std::vector<int> &hodge, const PrecOpts &o, int &r, std::vector<int> &Nm,
+                      int &M, std::string &err) {
     std::vector<int> slopes;
     for (int m = 1; m <= n; m++)
         for (int k = 0; k < hodge[m - 1]; k++) slopes.push_back(n - m);
@@ -257,8 +266,12 @@ bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_overrid
         err = "empty cohomology basis";
         return false;
     }
-    if (r_override > 0) {
-        r = r_override;
+    if (o.r < 0 || o.N < 0 || o.M < 0 || o.r > 64 || o.N > 64 || o.M > 128) {
+        err = "precision override out of range";
+        return false;
+    }
+    if (o.r > 0) {
+        r = o.r;
     } else {
         r = 1;
         int mu = slopes[0], h = 0;
@@ -270,12 +283,28 @@ bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_overrid
             r = std::max(r, std::min(rc, rp));
         }
     }
-    N = n_override > 0 ? n_override : r + 1;
+    const int N = o.N > 0 ? o.N : r + 1;
+    Nm.assign(n, N);
+    for (int m = 1; m <= n; m++) {
+        if (o.Nm[m - 1] < 0 || o.Nm[m - 1] > 64) {
+            err = "series order override out of range";
+            return false;
+        }
+        if (o.Nm[m - 1] > 0) Nm[m - 1] = o.Nm[m - 1];
+    }
     M = 0;
     for (int m = 1; m <= n; m++) {
         if (hodge[m - 1] == 0) continue;
-        int sm = N + m - 1;
+        int sm = Nm[m - 1] + m - 1;
         M = std::max(M, r + vp_fact((long long)p * sm - 1, p) - m + 1);
+    }
+    if (o.M > 0) {
+        if (o.M < M) {
+            err = "working precision M = " + std::to_string(o.M) + " is below the " + std::to_string(M) +
+                  " digits that keep r = " + std::to_string(r) + " digits in every column";
+            return false;
+        }
+        M = o.M;
     }
     return true;
 }
@@ -450,8 +479,8 @@ static std::vector<long long> multiplier_matrix(const Family &fam, const std::ve
     return A;
 }
 
-cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_override, int n_override,
-                     ItemSetup &out, std::string &err, bool smooth_only, bool host_psi) {
+cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, const PrecOpts &prec, ItemSetup &out,
+                     std::string &err, bool smooth_only, bool host_psi) {
     const int nv = fam.nv, n = fam.n, d = fam.d;
     if (!is_prime(p)) {
         err = "p is not prime";
@@ -545,7 +574,7 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         }
         hodge_generic[m - 1] = (int)hsz;
     }
-    if (!choose_precision(p, n, hodge_generic, r_override, n_override, out.r, out.N, out.M, err)) return CR_EINVAL;
+    if (!choose_precision(p, n, hodge_generic, prec, out.r, out.Nm, out.M, err)) return CR_EINVAL;
     {
         u128 q = 1;
         for (int k = 0; k < out.M; k++) {
@@ -667,13 +696,15 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
     }
     // Frobenius start terms (Proposition 2.1), grouped by the x^S-form exponent E'
     {
-        const int N = out.N, b = out.b;
-        std::vector<MonoSpace> psp(N);
-        std::vector<std::vector<u64>> fpow(N);
+        const int b = out.b;
+        int Nmax = 1;
+        for (int m = 1; m <= n; m++) Nmax = std::max(Nmax, out.Nm[m - 1]);
+        std::vector<MonoSpace> psp(Nmax);
+        std::vector<std::vector<u64>> fpow(Nmax);
         psp[0].init(nv, 0);
         fpow[0].assign(1, 1);
         int e[kMaxVars];
-        for (int j = 1; j < N; j++) {
+        for (int j = 1; j < Nmax; j++) {
             psp[j].init(nv, d * j);
             fpow[j].assign(psp[j].count, 0);
             for (int a = 0; a < psp[j - 1].count; a++) {
@@ -689,7 +720,8 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         // E' = p (gamma + 1) - 1 + 1_S with gamma = beta + alpha of degree d L - n - 1,
         // L = m + j = P / p: one dense slot table per pole level, indexed by the
         // rank of gamma (ranks run in lexicographically descending order)
-        const int nlev = n + N - 1;
+        int nlev = 1;
+        for (int m = 1; m <= n; m++) nlev = std::max(nlev, m + out.Nm[m - 1] - 1);
         std::vector<MonoSpace> lsp(nlev + 1);
         std::vector<std::vector<int>> slot(nlev + 1);
         for (int L = 1; L <= nlev; L++) {
@@ -699,9 +731,9 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
         std::vector<int> lev_of, rank_of;  // per distinct start term
         std::vector<u64> acc;              // nterm x b coefficients
         int col = 0;
-        std::vector<u64> scale(N);
+        std::vector<u64> scale(Nmax);
         for (int m = 1; m <= n; m++) {
-            const int sm = N + m - 1;
+            const int N = out.Nm[m - 1], sm = N + m - 1;
             // scale_j = D_{j,m} (p s_m - 1)! / (p (m + j) - 1)!, the same for every column of pole m
             u64 ratio = 1;
             long long t = (long long)p * sm - 1;
@@ -780,7 +812,7 @@ cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_ove
     std::vector<int> vm(n + 1, 0);
     std::vector<u64> unitm(n + 1, 1);
     for (int m = 1; m <= n; m++) {
-        const long long top = (long long)p * (out.N + m - 1) - 1;
+        const long long top = (long long)p * (out.Nm[m - 1] + m - 1) - 1;
         vm[m] = vp_fact(top, p);
         u64 unit = 1;
         for (long long t = n; t <= top; t++) {

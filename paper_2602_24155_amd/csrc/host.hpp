@@ -93,7 +93,8 @@ struct Family {
 
 // ---------------------------------------------------------------- per item
 struct ItemSetup {
-    int p = 0, r = 0, N = 0, M = 0, b = 0;
+    int p = 0, r = 0, M = 0, b = 0;
+    std::vector<int> Nm;             // series order N_m, m = 1..n (index m-1)
     ModQ mq;
     std::vector<int> hodge;          // |B_m|, m = 1..n (index m-1)
     std::vector<int> col_pole;       // b
@@ -112,16 +113,26 @@ struct ItemSetup {
     int nchain() const { return (int)chain_g.size(); }
 };
 
-// Precision of Section 2.5 under the reading in crfrob.h.
-bool choose_precision(int p, int n, const std::vector<int> &hodge, int r_override, int n_override,
-                      int &r, int &N, int &M, std::string &err);
+// Caller overrides of the precision parameters of Section 2.5 (cr_family).
+struct PrecOpts {
+    int r = 0;              // relative precision; 0 = derive
+    int N = 0;              // N_m for every m; 0 = r + 1
+    int Nm[kMaxVars] = {};  // N_m of pole order m = 1..n (index m-1); 0 = N
+    int M = 0;              // working precision; 0 = the least that keeps r digits in every column
+    static PrecOpts from(const cr_family *fam);
+};
+
+// Precision of Section 2.5 under the reading in crfrob.h: r, N_m (m = 1..n)
+// and M.  Fails (err set) if an override is out of range or M is below the
+// least working precision for r.
+bool choose_precision(int p, int n, const std::vector<int> &hodge, const PrecOpts &o, int &r, std::vector<int> &Nm,
+                      int &M, std::string &err);
 
 // S-smoothness test + full setup of one item.  Returns CR_OK or an error status.
 // With host_psi false the right inverse of J_S is not computed: out.J holds
 // J_S mod q for the device (k_psi), and a non-surjective J_S is reported there.
-cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, int r_override,
-                     int n_override, ItemSetup &out, std::string &err, bool smooth_only = false,
-                     bool host_psi = true);
+cr_status setup_item(const Family &fam, int p, const uint32_t *coeffs, const PrecOpts &prec, ItemSetup &out,
+                     std::string &err, bool smooth_only = false, bool host_psi = true);
 
 // Unscale the device result Y (b x b mod q) and recover Q(T).
 cr_status finish_item(const Family &fam, const ItemSetup &it, const u64 *Y, u64 *frob,

@@ -113,3 +113,41 @@ def test_closed_form_rank_of_three_variable_monomials(d):
         for idx, m in enumerate(mons):
             r = d - m[0]
             assert r * (r + 1) // 2 + (r - m[1]) == idx
+
+
+@pytest.mark.parametrize("nv,d,p", [(3, 4, 7), (3, 5, 31), (4, 4, 11)])
+def test_precision_overrides_match_oracle(nv, d, p):
+    """cr_family.M and cr_family.n_series_m (Section 2.5 / Proposition 2.1)
+    against the oracle's precision rule with the same overrides."""
+    from math import comb as _c
+    n = nv - 1
+    hodge = {m: sum((-1) ** j * _c(nv, j) * _c(d * m - n - 1 - j * (d - 1) + n, n)
+                    for j in range(nv) if d * m - n - 1 - j * (d - 1) >= 0) for m in range(1, n + 1)}
+    r, _Nm, _s, M = precision_parameters(p, n, hodge)
+    nm = [r + 1 + (m % 2) for m in range(1, n + 1)]
+    r2, Nm2, _s2, M2 = precision_parameters(p, n, hodge, N={m: nm[m - 1] for m in range(1, n + 1)})
+    assert C.cr_precision(C.family(nv, d, n_series_m=nm), p) == (r2, max(nm), M2)
+    assert C.cr_precision(C.family(nv, d, M=M + 2), p) == (r, r + 1, M + 2)
+    with pytest.raises(C.CrError) as e:
+        C.cr_precision(C.family(nv, d, M=M - 1), p)
+    assert e.value.status == C.CR_EINVAL
+    assert C.cr_residue_words(C.family(nv, d), p) == 1
+
+
+def test_residue_words_reject_wide_moduli():
+    # quintic surfaces over F_7 need p^M ~ 2^132: beyond the one-word residues
+    with pytest.raises(C.CrError) as e:
+        C.cr_residue_words(C.family(4, 5), 7)
+    assert e.value.status == C.CR_EPRECISION
+    with pytest.raises(C.CrError) as e:
+        C.cr_residue_words(C.family(3, 5, M=40), 31)
+    assert e.value.status == C.CR_EPRECISION
+
+
+def test_single_hypersurface_entry_rejects_bad_input_without_device():
+    with pytest.raises(C.CrError) as e:
+        C.cr_frobenius(C.family(3, 5), 31, [40] * 21)
+    assert e.value.status == C.CR_EINVAL
+    with pytest.raises(C.CrError) as e:
+        C.cr_frobenius(C.family(3, 5), 9, [1] * 21)
+    assert e.value.status in (C.CR_ENOTPRIME, C.CR_EINVAL)

@@ -90,14 +90,19 @@ def test_train_and_reduce_with_learned_policy():
     fam = C.family(3, 5, policy=C.CR_POLICY_LEARNED, mlp=m)
     res = C.cr_frobenius_batch(fam, [p for p, _ in items], [c for _, c in items])
     st = res["stats"]
-    assert st.policy == C.CR_POLICY_LEARNED and 0 <= st.fallbacks <= len(items)
+    # the judge kept at least one learned plan, so the forced-direction vectors ran on the device
+    assert st.policy == C.CR_POLICY_LEARNED and 0 <= st.fallbacks < len(items)
     for i, (p, c) in enumerate(items):
         assert_item_matches_oracle(res, i, 3, 5, p, c)
-    # judged plans never cost more column steps than the plain p-chunk plans
-    plain = sum(C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_P_CHUNK), p, c).column_steps
-                + C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_P_CHUNK), p, c).merged_terms / 8.0
-                for p, c in items)
-    assert st.column_steps + st.merged_terms / 8.0 <= plain + 1e-9
+    # judged plans never cost more than the plain p-chunk plans, and here cost less
+    pc = [C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_P_CHUNK), p, c) for p, c in items]
+    df = [C.cr_policy_cost(C.family(3, 5, policy=C.CR_POLICY_DEPTH_FIRST), p, c) for p, c in items]
+    plain = sum(x.column_steps + x.merged_terms / 8.0 for x in pc)
+    learned = st.column_steps + st.merged_terms / 8.0
+    print("column steps: learned %d, p-chunk %d, depth-first %d (fallbacks %d of %d)"
+          % (st.column_steps, sum(x.column_steps for x in pc), sum(x.column_steps for x in df), st.fallbacks,
+             len(items)))
+    assert learned < plain
     m.close()
 
 

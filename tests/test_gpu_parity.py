@@ -144,3 +144,44 @@ def test_release_regrow_and_invalid_items():
     assert st[0] == st[2] == st[4] == C.CR_OK and st[1] != C.CR_OK and st[3] != C.CR_OK
     for i, j in ((0, 0), (2, 1), (4, 2)):
         assert np.array_equal(res["scaled"][i], a["scaled"][j]) and res["lpoly"][i] == a["lpoly"][j]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("policy", [C.CR_POLICY_DEPTH_FIRST, C.CR_POLICY_P_CHUNK, C.CR_POLICY_VAR_BY_VAR])
+def test_s_mask_subsets(engine, policy):
+    """S a proper subset of the variables (Definition 3.1; Proposition 3.3 in
+    the x^S form): the device reduction with cr_family.s_mask against the
+    oracle run with the same S, bit for bit, for the quartic curve over F_7
+    and a quintic curve over F_37, several S each."""
+    from oracle.cohomology import is_s_smooth
+    if engine == C.ENGINE_MFMA_LDS and policy != C.CR_POLICY_DEPTH_FIRST:
+        pytest.skip("the LDS-gather kernel runs the depth-first policy only")
+    cases = [("quartic_curve_f7", 3, 4, 0, [[2], [0], [1, 2]]), ("quintic_curves_mixed", 3, 5, 1, [[0], [1, 2]])]
+    for name, nv, d, j, subsets in cases:
+        p, c = workload_items(name, [j])[0]
+        fp = {e: v % p for e, v in from_coeffs(nv, d, c).items() if v % p}
+        for S in subsets:
+            assert is_s_smooth(fp, nv, d, p, S)
+            mask = sum(1 << i for i in S)
+            res = run_batch(nv, d, [(p, c)], s_mask=mask, engine=engine, policy=policy)
+            o = frobenius(nv, d, p, c, S=S)
+            print("s_mask case", name, p, S, "engine", res["stats"].engine, flush=True)
+            assert_item_matches_oracle(res, 0, nv, d, p, c, oracle=o)
+
+
+@pytest.mark.parametrize("engine", [C.ENGINE_AUTO, C.ENGINE_VALU])
+def test_single_entry_and_precision_overrides(engine):
+    """cr_frobenius (one hypersurface) with the working precision M and the
+    per-pole series orders N_m overridden (Section 2.5, Proposition 2.1),
+    against the oracle run with the same overrides, bit for bit."""
+    for name, nv, d in (("quartic_curve_f7", 3, 4), ("quintic_curves_p31", 3, 5)):
+        p, c = workload_items(name, [0])[0]
+        r, N, M = C.cr_precision(C.family(nv, d), p)
+        cases = [({}, {}), ({"M": M + 2}, {"M": M + 2}), ({"n_series_m": [N + 1, N]}, {"N": {1: N + 1, 2: N}})]
+        for kw, okw in cases:
+            print("precision case", name, kw, flush=True)
+            one = C.cr_frobenius(C.family(nv, d, engine=engine, **kw), p, c)
+            res = {k: [v] for k, v in one.items() if k in ("frob", "scaled", "col_pole", "col_prec", "lpoly")}
+            res["item_status"] = [one["status"]]
+            o = frobenius(nv, d, p, c, **okw)
+            assert_item_matches_oracle(res, 0, nv, d, p, c, oracle=o)

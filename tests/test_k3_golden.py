@@ -47,6 +47,17 @@ def test_golden_lpolys_satisfy_weil_and_point_counts():
         assert point_counts_from_lpoly(a, p, 3, 1) == [count_projective(f, 4, p, 1)]
 
 
+def test_golden_lpolys_match_counts_over_f_p2():
+    """#X(F_{p^2}) by brute force (per-line root counts over F_{p^2}) fixes the
+    power sum s_2 of the Frobenius eigenvalues, a second independent
+    combination of the stored coefficients (a_1^2 - 2 a_2)."""
+    for it in golden():
+        p = it["p"]
+        a = [int(x) for x in it["lpoly"]]
+        f = {e: v % p for e, v in from_coeffs(4, 4, it["coeffs"]).items() if v % p}
+        assert point_counts_from_lpoly(a, p, 3, 2) == [count_projective(f, 4, p, k) for k in (1, 2)]
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("policy", [C.CR_POLICY_DEPTH_FIRST, C.CR_POLICY_P_CHUNK, C.CR_POLICY_VAR_BY_VAR])
 def test_gpu_matches_golden(policy):

@@ -99,6 +99,48 @@ def test_permutation_invariance():
     assert res2.lpoly == res.lpoly
 
 
+@pytest.mark.parametrize("name,nv,d,j,subsets", [
+    ("quartic_curve_f7", 3, 4, 0, [[2], [0], [1], [1, 2], [0, 2]]),
+    ("quintic_curves_mixed", 3, 5, 1, [[0], [1], [1, 2], [0, 2]]),
+])
+def test_s_subsets_give_the_s_all_result(name, nv, d, j, subsets):
+    """Definition 3.1 / Proposition 3.3 with S a proper subset: the reduction
+    runs in the x^S form (sources of J_S for i not in S are x_i d_i f, the
+    R_{u,v} weight of those rows is u_i + 1, Algorithm 3 forces v_i >= 1 only
+    for i in S, target norm |S| - 1), but every step is still an identity in
+    cohomology, so the scaled coordinates and Q(T) equal those of S = all."""
+    p, c = workload.first_accepted(name, j, lambda p, c: _smooth(nv, d, p, c))
+    base = frobenius(nv, d, p, c)
+    from oracle.cohomology import is_s_smooth
+    fp = {e: v % p for e, v in from_coeffs(nv, d, c).items() if v % p}
+    ran = 0
+    for S in subsets:
+        if not is_s_smooth(fp, nv, d, p, S):
+            with pytest.raises(ValueError):
+                frobenius(nv, d, p, c, S=S)
+            continue
+        res = frobenius(nv, d, p, c, S=S)
+        assert res.M == base.M
+        assert np.array_equal(res.scaled, base.scaled), S
+        assert res.lpoly == base.lpoly
+        ran += 1
+    assert ran >= 3
+
+
+def test_s_subset_on_a_k3_column():
+    """A quartic K3 surface of the stored goldens (pinned by point counts)
+    reduced in the x^S form with S = {2, 3}: the m = 1 column equals the
+    stored S = all column (columns never mix, so one column is exact)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "k3_golden.json")
+    with open(path) as fh:
+        it = [x for x in json.load(fh)["items"] if x["p"] == 7][0]
+    res = frobenius(4, 4, 7, it["coeffs"], S=[2, 3], columns=[0], lpoly=False)
+    assert res.col_pole[0] == 1
+    assert [int(res.scaled[i][0]) for i in range(21)] == [int(row[0]) for row in it["scaled"]]
+
+
 def test_convergence_one_more_term():
     c, res = _random_smooth(3, 4, 7, 13)
     r = res.r
