@@ -212,6 +212,31 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
 cr_status cr_frobenius(const cr_family *fam, int32_t p, const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
                        int32_t *col_pole, int32_t *col_prec, int64_t *lpoly, cr_stats *stats, void *hip_stream);
 
+/* For callers that cannot allocate device memory (work inside their own HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments, outputs and per-item statuses as
+ * cr_frobenius_batch, with every device buffer taken from one static
+ * workspace of CR_NOALLOC_WORKSPACE_BYTES bytes inside the library (each
+ * device holds its own copy from the first call on it until the process
+ * ends).  The call makes no hipMalloc / hipFree / hipHostMalloc and creates
+ * no stream or graph: host staging is pageable memory and every copy and
+ * kernel runs on hip_stream.  The call's right inverses of J_S take the
+ * front of the workspace and each sub-batch in turn the rest (so the host's
+ * preparation of a sub-batch does not overlap the device work of the one
+ * before); when they do not fit, the call fails with CR_ENOMEM and
+ * cr_last_error() gives the bytes needed and held (a sub-batch of 24 plane
+ * quintics under p-chunk needs about 82 MB).
+ * CR_POLICY_LEARNED and launch mode 2 are rejected (CR_EINVAL).  Every call
+ * on a device uses the same workspace and leaves its contents behind; each
+ * call clears what must start at zero and returns only after its device work
+ * is done.  Calls of one process are serialised by the library's lock; two
+ * calls that overlapped on one device would race on the workspace. */
+#define CR_NOALLOC_WORKSPACE_BYTES (128ull << 20)
+cr_status cr_frobenius_batch_noalloc(const cr_family *fam, int32_t count, const int32_t *primes,
+                                     const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole,
+                                     int32_t *col_prec, int64_t *lpoly, int32_t *item_status, cr_stats *stats,
+                                     void *hip_stream);
+
 /* Host-only planning of one hypersurface under fam->policy (no device work):
  * fills start_blocks, column_steps, chunks, vectors, merged_terms,
  * combined_groups, phases and policy of *stats (the game cost of Section 3.4

@@ -8,7 +8,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcrfrob.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["host.cpp", "plan.cpp", "capi.cpp", "mlp_api.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip", "psi.hip"]
+SOURCES = ["host.cpp", "plan.cpp", "capi.cpp", "mlp_api.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip", "psi.hip",
+           "workspace.hip"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

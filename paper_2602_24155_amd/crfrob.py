@@ -17,7 +17,7 @@ CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
 CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_residue_words", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_frobenius", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
+           "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
            "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_autotune", "cr_release",
            "cr_last_error"]
 
@@ -81,6 +81,7 @@ def lib():
                                    P(cr_stats), ctypes.c_void_p]
         L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
                                          P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
+        L.cr_frobenius_batch_noalloc.argtypes = L.cr_frobenius_batch.argtypes
         L.cr_policy_cost.argtypes = [P(cr_family), i32, P(u32), P(cr_stats)]
         f32, vp = ctypes.c_float, ctypes.c_void_p
         L.cr_mlp_create.argtypes = [P(f32), u64, P(vp)]
@@ -167,10 +168,12 @@ def _lpoly_ints(words):
     return out
 
 
-def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise_on_error=True, lpoly_ints=True):
+def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise_on_error=True, lpoly_ints=True,
+                       noalloc=False):
     """Run the whole path for a batch; returns a dict of numpy arrays / lists.
     With lpoly_ints=False, "lpoly" is the raw (count, b+1, 4) array of 256-bit
-    two's-complement words instead of lists of Python integers."""
+    two's-complement words instead of lists of Python integers.  noalloc=True
+    calls cr_frobenius_batch_noalloc (the static device workspace)."""
     primes = np.ascontiguousarray(np.asarray(primes, dtype=np.int32))
     count = int(primes.shape[0])
     nco, _s, b = cr_query_dims(fam.nvars, fam.degree)
@@ -182,7 +185,8 @@ def cr_frobenius_batch(fam, primes, coeffs, stream=None, want_scaled=True, raise
     lp = np.zeros((count, b + 1, 4), dtype=np.int64)
     ist = np.zeros(count, dtype=np.int32)
     stats = cr_stats()
-    st = lib().cr_frobenius_batch(ctypes.byref(fam), count, _ptr(primes, ctypes.c_int32),
+    fn = lib().cr_frobenius_batch_noalloc if noalloc else lib().cr_frobenius_batch
+    st = fn(ctypes.byref(fam), count, _ptr(primes, ctypes.c_int32),
                                   _ptr(co, ctypes.c_uint32), _ptr(frob, ctypes.c_uint64),
                                   _ptr(scaled, ctypes.c_uint64) if scaled is not None else None,
                                   _ptr(pole, ctypes.c_int32), _ptr(prec, ctypes.c_int32),

@@ -74,13 +74,30 @@ cr_status fail(cr_status st, const std::string &msg) {
 
 // ------------------------------------------------------------ device memory
 // One grow-only device buffer and one pinned host staging buffer, reused by
-// every call (calls are serialised by g_mutex).
+// every call (calls are serialised by g_mutex).  A fixed arena (the
+// allocation-free entry point) is a slice of the static device workspace
+// with pageable host staging: it never allocates device or pinned memory and
+// fails when a request exceeds its slice.
 struct Arena {
     void *dev = nullptr;
     size_t dev_cap = 0;
     void *host = nullptr;
     size_t host_cap = 0;
+    bool fixed = false;
+    std::vector<unsigned char> host_heap;  // host staging of a fixed arena
+    void bind(void *slice, size_t bytes) {
+        fixed = true;
+        dev = slice;
+        dev_cap = bytes;
+    }
     bool ensure(size_t dbytes, size_t hbytes) {
+        if (fixed) {
+            if (dbytes > dev_cap) return false;
+            if (hbytes > host_heap.size()) host_heap.resize(hbytes);
+            host = host_heap.data();
+            host_cap = host_heap.size();
+            return true;
+        }
         if (dbytes > dev_cap) {
             const size_t cap = std::max(dbytes, dev_cap + dev_cap / 2);
             if (dev) (void)hipFree(dev);
@@ -100,6 +117,7 @@ struct Arena {
         return true;
     }
     void release() {
+        if (fixed) return;
         if (dev) (void)hipFree(dev);
         if (host) (void)hipHostFree(host);
         dev = host = nullptr;
@@ -397,11 +415,28 @@ struct BatchCtx {
     hipStream_t stream = nullptr;
     // device psi: one k_psi launch for every item of the call, at its start
     uint64_t *psi_dev = nullptr;         // count x (nsrc x T), caller's item order
+    size_t psi_bytes = 0;                // device bytes of the call's psi region
     const int32_t *psi_flags = nullptr;  // host copy of k_psi's per-item flags (after psi_done)
     hipEvent_t psi_t0 = nullptr, psi_done = nullptr;
     const int32_t *primes = nullptr;
     const uint32_t *coeffs = nullptr;
     Outputs out{};
+    // the allocation-free entry point binds these to slices of the static
+    // workspace and runs everything on the caller's stream
+    bool noalloc = false;
+    Arena *arenas[kArenas] = {&g_arenas[0], &g_arenas[1]};
+    Arena *psi_arena = &g_psi_arena;
+    // stream of the uploads and psi work that overlap the reductions
+    hipError_t aux(hipStream_t &out_stream) {
+        if (noalloc) {
+            out_stream = stream;
+            return hipSuccess;
+        }
+        hipError_t e = hipSuccess;
+        if (!g_aux) e = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
+        out_stream = g_aux;
+        return e;
+    }
     bool init(const cr_family *f, const int32_t *pr, const uint32_t *co, hipStream_t s, std::string &err) {
         fam = f;
         primes = pr;
@@ -682,9 +717,11 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     sb.o_hbuf = take(8 * (size_t)F.fin.count * nvec);
     sb.o_store = take(8 * (size_t)sdim * std::max<size_t>(nrows, 1));
     const size_t d_end = off;
-    Arena &ar = g_arenas[sb.arena];
+    Arena &ar = *ctx.arenas[sb.arena];
     if (!ar.ensure(d_end, sb.o_Y + 8 * (size_t)b * b * nlive)) {
-        msg = "device or pinned host allocation failed";
+        msg = ar.fixed ? "the sub-batch needs " + std::to_string(d_end) + " bytes of device memory; its slice of the "
+                         "static workspace holds " + std::to_string(ar.dev_cap)
+                       : "device or pinned host allocation failed";
         return CR_ENOMEM;
     }
     unsigned char *hb = static_cast<unsigned char *>(ar.host);
@@ -825,7 +862,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
 cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     if (sb.live.empty()) return CR_OK;
     hipStream_t stream = ctx.stream;
-    Arena &ar = g_arenas[sb.arena];
+    Arena &ar = *ctx.arenas[sb.arena];
     unsigned char *hb = static_cast<unsigned char *>(ar.host);
     unsigned char *db = static_cast<unsigned char *>(ar.dev);
     const DevFamily &df = sb.df;
@@ -840,15 +877,16 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         // order on the auxiliary stream, behind the call's k_psi launch; this
         // overlaps the reduction of the previous sub-batch (whose arena is the
         // other one); the main stream waits for it before the reductions
-        if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
+        hipStream_t aux = nullptr;
+        he = ctx.aux(aux);
         (void)hipEventCreate(&sb.epe);
-        if (he == hipSuccess) he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, g_aux);
+        if (he == hipSuccess) he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, aux);
         const DevItem *dv = reinterpret_cast<const DevItem *>(db + sb.o_items);
         if (he == hipSuccess && sb.use_mfma)
             he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
                                  reinterpret_cast<const int16_t *>(db + sb.o_tables + ctx.fe->off_slot_src), ctx.nrt,
-                                 ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, sb.use_pairs ? 1 : 0, g_aux);
-        (void)hipEventRecord(sb.epe, g_aux);
+                                 ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, sb.use_pairs ? 1 : 0, aux);
+        (void)hipEventRecord(sb.epe, aux);
         if (he == hipSuccess) he = hipStreamWaitEvent(stream, sb.epe, 0);
     } else {
         he = hipMemcpyAsync(db, hb, sb.h_end, hipMemcpyHostToDevice, stream);
@@ -990,7 +1028,7 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
         msg = std::string("HIP error: ") + hipGetErrorString(he);
         return CR_EDEVICE;
     }
-    unsigned char *hb = static_cast<unsigned char *>(g_arenas[sb.arena].host);
+    unsigned char *hb = static_cast<unsigned char *>(ctx.arenas[sb.arena]->host);
     int derr;
     std::memcpy(&derr, hb + sb.o_err, 4);
     if (derr) {
@@ -1185,12 +1223,16 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     const size_t o_flags = take(4 * (size_t)count);
     const size_t h_end = off;
     const size_t o_psi = take(8 * psi_len * count);
-    if (!g_psi_arena.ensure(off, h_end)) {
-        msg = "device or pinned host allocation failed";
+    Arena &ar = *ctx.psi_arena;
+    if (!ar.ensure(off, h_end)) {
+        msg = ar.fixed ? "the right inverses of J_S need " + std::to_string(off) + " bytes of device memory; the "
+                         "static workspace holds " + std::to_string(ar.dev_cap)
+                       : "device or pinned host allocation failed";
         return CR_ENOMEM;
     }
-    unsigned char *hb = static_cast<unsigned char *>(g_psi_arena.host);
-    unsigned char *db = static_cast<unsigned char *>(g_psi_arena.dev);
+    ctx.psi_bytes = off;
+    unsigned char *hb = static_cast<unsigned char *>(ar.host);
+    unsigned char *db = static_cast<unsigned char *>(ar.dev);
     std::memcpy(hb + o_jtab, F.jtab.data(), 4 * F.jtab.size());
     std::memcpy(hb + o_coef, ctx.coeffs, 4 * (size_t)count * nco);
     std::memset(hb + o_flags, 0, 4 * (size_t)count);
@@ -1226,18 +1268,18 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
         di.psi_out = reinterpret_cast<uint64_t *>(db + o_psi) + psi_len * g;
         di.flag = reinterpret_cast<int32_t *>(db + o_flags) + g;
     }
-    hipError_t he = hipSuccess;
-    if (!g_aux) he = hipStreamCreateWithFlags(&g_aux, hipStreamNonBlocking);
+    hipStream_t aux = nullptr;
+    hipError_t he = ctx.aux(aux);
     (void)hipEventCreate(&ctx.psi_t0);
     (void)hipEventCreate(&ctx.psi_done);
-    if (he == hipSuccess) he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, g_aux);
-    (void)hipEventRecord(ctx.psi_t0, g_aux);
+    if (he == hipSuccess) he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, aux);
+    (void)hipEventRecord(ctx.psi_t0, aux);
     if (he == hipSuccess)
         he = launch_psi(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
-                        reinterpret_cast<const int32_t *>(db + o_jtab), g_aux);
+                        reinterpret_cast<const int32_t *>(db + o_jtab), aux);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(hb + o_flags, db + o_flags, 4 * (size_t)count, hipMemcpyDeviceToHost, g_aux);
-    (void)hipEventRecord(ctx.psi_done, g_aux);
+        he = hipMemcpyAsync(hb + o_flags, db + o_flags, 4 * (size_t)count, hipMemcpyDeviceToHost, aux);
+    (void)hipEventRecord(ctx.psi_done, aux);
     if (he != hipSuccess) {
         msg = std::string("HIP error: ") + hipGetErrorString(he);
         return CR_EDEVICE;
@@ -1247,19 +1289,46 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     return CR_OK;
 }
 
-cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
-                             uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole, int32_t *col_prec,
-                             int64_t *lpoly, int32_t *item_status, cr_stats *stats, void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+hipError_t static_ws(void **ptr, size_t *bytes);
+
+// cr_frobenius_batch, and with noalloc its allocation-free variant (fixed
+// arenas in the static workspace, every stream operation on the caller's
+// stream, no graph capture, no model buffers).
+cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
+                          uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole, int32_t *col_prec, int64_t *lpoly,
+                          int32_t *item_status, cr_stats *stats, void *hip_stream, bool noalloc) {
     std::string err;
     if (!check_family(fam, err)) return fail(CR_EINVAL, err);
     if (count < 0 || (count > 0 && (!primes || !coeffs || !frob || !col_pole || !col_prec || !lpoly)))
         return fail(CR_EINVAL, "null output or input pointer");
     if (count == 0) return CR_OK;
     if (fam->policy == CR_POLICY_LEARNED && !fam->mlp) return fail(CR_EINVAL, "CR_POLICY_LEARNED needs a model (cr_family.mlp)");
+    if (noalloc && fam->policy == CR_POLICY_LEARNED)
+        return fail(CR_EINVAL, "the allocation-free entry point does not run CR_POLICY_LEARNED (the network's row "
+                               "buffers grow with the batch)");
+    if (noalloc && fam->launch == 2)
+        return fail(CR_EINVAL, "the allocation-free entry point does not capture graphs (launch mode 2)");
     std::lock_guard<std::mutex> lk(g_mutex);
     BatchCtx ctx;
     if (!ctx.init(fam, primes, coeffs, reinterpret_cast<hipStream_t>(hip_stream), err)) return fail(CR_EINVAL, err);
     ctx.out = {frob, frob_scaled, col_pole, col_prec, lpoly};
+    Arena fixed[kArenas], fixed_psi;
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0;
+    if (noalloc) {
+        void *wp = nullptr;
+        const hipError_t he = static_ws(&wp, &ws_bytes);
+        if (he != hipSuccess) return fail(CR_EDEVICE, std::string("static workspace: ") + hipGetErrorString(he));
+        ws = static_cast<unsigned char *>(wp);
+        ctx.noalloc = true;
+        fixed_psi.bind(ws, ws_bytes);
+        ctx.psi_arena = &fixed_psi;
+        for (int k = 0; k < kArenas; k++) ctx.arenas[k] = &fixed[k];
+    }
     // Sub-batches: the host prepares sub-batch k + 1 while the device reduces
     // sub-batch k.  Sizes follow the width P of the host pool (each item's
     // setup is one task): the first sub-batch, whose host setup and psi the
@@ -1276,7 +1345,7 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
     std::vector<SubBatch> sub(S);
     for (int k = 0; k < S; k++) {
         for (int i = cut[k]; i < cut[k + 1]; i++) sub[k].idx.push_back(i);
-        sub[k].arena = k % kArenas;
+        sub[k].arena = noalloc ? 0 : k % kArenas;
     }
     std::vector<cr_status> st(count, CR_OK);
     std::vector<std::string> errs(count);
@@ -1305,19 +1374,27 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
             return fail(fatal, fatal_msg);
         }
     }
+    // Without the workspace every sub-batch has its own arena of two, and
+    // complete(k - 1) releases the arena that sub-batch k + 1 reuses; with it,
+    // one arena (what the call's psi leaves of the workspace) serves every
+    // sub-batch in turn, each completed before the next is prepared.
+    const int lag = noalloc ? 0 : kArenas - 1;
+    if (noalloc) {
+        const size_t used = align256(ctx.psi_bytes);
+        fixed[0].bind(ws + used, used < ws_bytes ? ws_bytes - used : 0);
+    }
     auto stop_all = [&](int upto) {  // drain the device before reporting a failure
         (void)hipStreamSynchronize(ctx.stream);
         if (g_aux) (void)hipStreamSynchronize(g_aux);
         for (int k = 0; k <= upto && k < S; k++) sub[k].destroy_events();
     };
-    // complete(k - kArenas + 1) releases the arena that sub-batch k + 1 reuses.
     for (int k = 0; k < S && fatal == CR_OK; k++) {
         fatal = prepare_sub(ctx, sub[k], fatal_msg);
         if (fatal == CR_OK) fatal = launch_sub(ctx, sub[k], fatal_msg);
-        if (fatal == CR_OK && k >= kArenas - 1) fatal = complete_sub(ctx, sub[k - (kArenas - 1)], st, errs, fatal_msg);
+        if (fatal == CR_OK && k >= lag) fatal = complete_sub(ctx, sub[k - lag], st, errs, fatal_msg);
         if (fatal != CR_OK) stop_all(k);
     }
-    for (int k = std::max(0, S - (kArenas - 1)); k < S && fatal == CR_OK; k++)
+    for (int k = std::max(0, S - lag); k < S && fatal == CR_OK; k++)
         fatal = complete_sub(ctx, sub[k], st, errs, fatal_msg);
     if (fatal != CR_OK) {
         stop_all(S - 1);
@@ -1370,6 +1447,33 @@ cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t 
         stats->device_ms += psi_all_ms;
     }
     return first;
+}
+
+}  // namespace
+
+namespace crf {
+hipError_t static_workspace(void **ptr, size_t *bytes);
+}
+
+namespace {
+hipError_t static_ws(void **ptr, size_t *bytes) { return crf::static_workspace(ptr, bytes); }
+}  // namespace
+
+extern "C" {
+
+cr_status cr_frobenius_batch(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
+                             uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole, int32_t *col_prec,
+                             int64_t *lpoly, int32_t *item_status, cr_stats *stats, void *hip_stream) {
+    return frobenius_batch(fam, count, primes, coeffs, frob, frob_scaled, col_pole, col_prec, lpoly, item_status,
+                           stats, hip_stream, false);
+}
+
+cr_status cr_frobenius_batch_noalloc(const cr_family *fam, int32_t count, const int32_t *primes,
+                                     const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled, int32_t *col_pole,
+                                     int32_t *col_prec, int64_t *lpoly, int32_t *item_status, cr_stats *stats,
+                                     void *hip_stream) {
+    return frobenius_batch(fam, count, primes, coeffs, frob, frob_scaled, col_pole, col_prec, lpoly, item_status,
+                           stats, hip_stream, true);
 }
 
 cr_status cr_frobenius(const cr_family *fam, int32_t p, const uint32_t *coeffs, uint64_t *frob, uint64_t *frob_scaled,
