@@ -95,11 +95,15 @@ typedef struct {
                          the accumulators and two interleaved tiles per workgroup -- the
                          products of one tile overlap the finishing of the other -- when the
                          family and digit count allow it, else the same kernel with one tile per
-                         workgroup, else the 64-bit VALU kernel), 1 = 64-bit VALU kernel,
-                         2 = int8-digit MFMA kernel with the gather through LDS, 3 = register-
-                         gather MFMA kernel with one tile per workgroup */
-    int32_t launch;   /* reduction launches (int8-digit register-gather kernel; the others always
-                         use mode 0): 0 = one workgroup per tile of 32 vectors; 1 = persistent:
+                         workgroup, for four-variable families with S = all (quartic K3
+                         surfaces) the quad kernel, else the 64-bit VALU kernel), 1 = 64-bit VALU
+                         kernel, 2 = int8-digit MFMA kernel with the gather through LDS, 3 =
+                         register-gather MFMA kernel with one tile per workgroup, 4 = quad
+                         kernel: int8-digit MFMA for four variables, psi digits streamed from
+                         memory row tile by row tile, the gather on the accumulators (each
+                         output's source rows in one lane's aligned quad of rows) */
+    int32_t launch;   /* reduction launches (int8-digit register-gather and quad kernels; the
+                         others always use mode 0): 0 = one workgroup per tile of 32 vectors; 1 = persistent:
                          one grid sized to the device's resident capacity drains the tiles
                          (longest first) through an atomic counter; 2 = as 1, with the launches
                          of a sub-batch captured once into a hipGraph and replayed while the
@@ -130,7 +134,8 @@ typedef struct {
     double assemble_ms;      /* device time of the Griffiths-Dwork assembly kernel */
     double finish_ms;        /* host unscaling and L-polynomial recovery */
     int32_t engine;          /* kernel that ran: 0 / 3 / 2 = int8-digit MFMA (register gather with tile
-                                pairs / with one tile / LDS gather), 1 = 64-bit VALU */
+                                pairs / with one tile / LDS gather), 4 = int8-digit MFMA quad kernel
+                                (four variables), 1 = 64-bit VALU */
     int32_t policy;          /* policy whose plan ran */
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
     int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a
@@ -313,6 +318,43 @@ typedef struct {
 } cr_tuning;
 cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
                       int32_t trials, cr_tuning *out, void *hip_stream);
+
+/*
+ * Newton-polygon invariants of Q(T) (host only; Sections 1.2, 6.3, 6.4, 6.6).
+ * The Newton polygon is the lower convex hull of the points (j, v_p(a_j)) of
+ * the nonzero coefficients of Q(T); the Hodge polygon of the basis has slope
+ * n - m with multiplicity h_m (pole order m, Section 2.3), and lies below it
+ * (Mazur).  Segments are reported left to right with integer rise over
+ * length (the vertices are lattice points), collinear pieces merged.
+ *   p_rank        length of the Newton segment whose slope is the least Hodge
+ *                 slope (slope 0 for curves: the p-rank of the Jacobian;
+ *                 slope 1 for cubic threefolds)
+ *   ordinary      Newton polygon = Hodge polygon
+ *   supersingular one slope, w/2 (w = n - 1 the weight)
+ *   height        for Hodge numbers 1, b - 2, 1 around the middle slope w/2
+ *                 (quartic K3 surfaces: the Artin-Mazur height; cubic
+ *                 fourfolds: the Newton height): the h with first Newton slope
+ *                 w/2 - 1/h; 0 = infinite (supersingular); -1 = not defined
+ *   domino        surfaces (nvars = 4): the least vertical distance between
+ *                 the Newton and the Hodge polygon over the slope-1 part of
+ *                 the Hodge polygon, as domino_num / domino_den (0 = Hodge-
+ *                 Witt); domino_num = -1 for other dimensions
+ * lpoly: Q(T) as cr_frobenius_batch writes it ((b + 1) x 4 words, a_0 = 1),
+ * b = the basis size of (nvars, degree).  CR_EINVAL for bad arguments or a
+ * polynomial without a_0 = 1 or a nonzero a_b.
+ */
+#define CR_NEWTON_MAX 256
+typedef struct {
+    int32_t b;
+    int32_t nseg;
+    int32_t seg_len[CR_NEWTON_MAX];
+    int32_t seg_rise[CR_NEWTON_MAX];
+    int32_t p_rank;
+    int32_t ordinary, supersingular;
+    int32_t height;
+    int32_t domino_num, domino_den;
+} cr_newton;
+cr_status cr_newton_polygon(int32_t nvars, int32_t degree, int32_t p, const int64_t *lpoly, cr_newton *out);
 
 /* Frees the library's cached device and host workspaces. */
 cr_status cr_release(void);

@@ -140,3 +140,46 @@ def weil_root_check(a, p, w, rtol=1e-6):
     roots = np.roots(coeffs)
     target = float(p) ** (w / 2.0)
     return bool(np.all(np.abs(np.abs(roots) / target - 1.0) < rtol))
+
+
+def _poly_divmod(num, den):
+    """Quotient and remainder of polynomials over Q (coefficient lists, lowest
+    degree first, Fractions)."""
+    num = list(num)
+    q = [Fraction(0)] * max(1, len(num) - len(den) + 1)
+    while len(num) >= len(den) and any(num):
+        k = len(num) - len(den)
+        c = num[-1] / den[-1]
+        q[k] = c
+        for i, d in enumerate(den):
+            num[i + k] -= c * d
+        num.pop()
+        while num and num[-1] == 0:
+            num.pop()
+    return q, num
+
+
+def squarefree_part(a):
+    """Q / gcd(Q, Q') over Q: the same roots, each once (exact, Fractions)."""
+    f = [Fraction(x) for x in a]
+    while f and f[-1] == 0:
+        f.pop()
+    df = [i * f[i] for i in range(1, len(f))]
+    g, h = f, df
+    while h and any(h):
+        _, r = _poly_divmod(g, h)
+        g, h = h, r
+    q, r = _poly_divmod(f, g)
+    assert not any(r)
+    return q
+
+
+def weil_root_check_squarefree(a, p, w, rtol=1e-6):
+    """weil_root_check on the squarefree part of Q(T): repeated roots (common
+    on the algebraic classes of a surface, alpha = p times a root of unity)
+    are found to only about a cube root of the working precision by a
+    numerical root finder; removing the repetition first keeps the check
+    within rtol."""
+    sq = squarefree_part(a)
+    lead = sq[0]
+    return weil_root_check([x / lead for x in sq], p, w, rtol)

@@ -17,7 +17,7 @@ CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
 CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_residue_words", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
+           "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_newton_polygon", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
            "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_autotune", "cr_release",
            "cr_last_error"]
 
@@ -41,6 +41,16 @@ class cr_train_opts(ctypes.Structure):
 
 
 CR_MLP_INPUTS, CR_MLP_HIDDEN, CR_MLP_PARAMS = 16, 128, 18817
+
+
+CR_NEWTON_MAX = 256
+
+
+class cr_newton(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int32), ("nseg", ctypes.c_int32),
+                ("seg_len", ctypes.c_int32 * CR_NEWTON_MAX), ("seg_rise", ctypes.c_int32 * CR_NEWTON_MAX),
+                ("p_rank", ctypes.c_int32), ("ordinary", ctypes.c_int32), ("supersingular", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("domino_num", ctypes.c_int32), ("domino_den", ctypes.c_int32)]
 
 
 class cr_stats(ctypes.Structure):
@@ -82,6 +92,7 @@ def lib():
         L.cr_frobenius_batch.argtypes = [P(cr_family), i32, P(i32), P(u32), P(u64), P(u64), P(i32),
                                          P(i32), P(i64), P(i32), P(cr_stats), ctypes.c_void_p]
         L.cr_frobenius_batch_noalloc.argtypes = L.cr_frobenius_batch.argtypes
+        L.cr_newton_polygon.argtypes = [i32, i32, i32, P(i64), P(cr_newton)]
         L.cr_policy_cost.argtypes = [P(cr_family), i32, P(u32), P(cr_stats)]
         f32, vp = ctypes.c_float, ctypes.c_void_p
         L.cr_mlp_create.argtypes = [P(f32), u64, P(vp)]
@@ -110,7 +121,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS, ENGINE_MFMA_SINGLE = 0, 1, 2, 3
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS, ENGINE_MFMA_SINGLE, ENGINE_QUAD = 0, 1, 2, 3, 4
 
 
 LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
@@ -218,6 +229,31 @@ def cr_frobenius(fam, p, coeffs, stream=None, want_scaled=True, raise_on_error=T
         _check(st)
     return {"status": st, "frob": frob, "scaled": scaled, "col_pole": pole, "col_prec": prec,
             "lpoly": _lpoly_ints(lp), "stats": stats}
+
+
+def lpoly_words(a):
+    """Q(T) coefficients (Python integers) as the (b+1, 4) array of signed 256-bit
+    two's-complement words that the library writes."""
+    out = np.zeros((len(a), 4), dtype=np.int64)
+    for i, x in enumerate(a):
+        v = int(x) & ((1 << 256) - 1)
+        for k in range(4):
+            w = (v >> (64 * k)) & ((1 << 64) - 1)
+            out[i, k] = w - (1 << 64) if w >= 1 << 63 else w
+    return out
+
+
+def cr_newton_polygon(nvars, degree, p, words, raise_on_error=True):
+    """Newton-polygon invariants of Q(T) (host only): the cr_newton record, or
+    None on error when raise_on_error is False."""
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.int64).reshape(-1, 4))
+    out = cr_newton()
+    st = lib().cr_newton_polygon(nvars, degree, p, _ptr(w, ctypes.c_int64), ctypes.byref(out))
+    if st != CR_OK:
+        if raise_on_error:
+            _check(st)
+        return None
+    return out
 
 
 def cr_policy_cost(fam, p, coeffs):

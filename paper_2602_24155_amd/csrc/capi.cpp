@@ -51,6 +51,12 @@ hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int3
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
                            int nrt, int nkb, int T, int nsrc, int fold, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
+bool quad_shape(const DevFamily &fam, int &nrt, int &nrtf, int &nkb);
+bool quad_supports_digits(int D);
+hipError_t launch_reduce_quad(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, int pgrid,
+                              int *queue, hipStream_t stream);
 }  // namespace crf
 
 using namespace crf;
@@ -128,9 +134,11 @@ struct Arena {
 struct FamilyEntry {
     Family fam;
     std::vector<unsigned char> tables;  // packed device tables (host copy)
-    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src;
+    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src, off_qslots;
     BinLayout bl;  // source-row placement for the register-gather MFMA kernel
     bool bl_ok = false;
+    BinLayout ql;  // row placement of the four-variable quad kernel
+    bool ql_ok = false;
 };
 
 std::mutex g_mutex;
@@ -177,6 +185,8 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         shape.s = F.g.count;
         shape.ndir = F.dirs.count;
         shape.nv = F.nv;
+        shape.smask = F.smask;
+        shape.nfinU = F.finU.count;
         int nrt = 0, nkb = 0;
         e->bl_ok = mfma4_shape(shape, nrt, nkb) && bin_layout(F, nrt, e->bl);
         if (!e->bl_ok) e->bl.slot.assign(16, 0);
@@ -184,6 +194,10 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         std::vector<int16_t> ss(e->bl.slot_src.begin(), e->bl.slot_src.end());
         if (ss.empty()) ss.assign(16, -1);
         e->off_slot_src = put(ss.data(), ss.size() * 2);
+        int qrt = 0, qrtf = 0, qkb = 0;
+        e->ql_ok = quad_shape(shape, qrt, qrtf, qkb) && quad_layout(F, qrt, qrtf, e->ql);
+        if (!e->ql_ok) e->ql.slot.assign(16, 0);
+        e->off_qslots = put(e->ql.slot.data(), e->ql.slot.size() * 4);
     }
     auto *raw = e.get();
     g_families.emplace(key, std::move(e));
@@ -294,7 +308,7 @@ bool check_family(const cr_family *fam, std::string &err) {
         err = "unsupported nvars/degree";
         return false;
     }
-    if (fam->engine < 0 || fam->engine > 3) {
+    if (fam->engine < 0 || fam->engine > 4) {
         err = "unknown engine";
         return false;
     }
@@ -410,6 +424,7 @@ struct BatchCtx {
     DevFamily df{};
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
+    bool quad = false;        // four-variable int8-digit MFMA kernel (k_reduce_quad)
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
@@ -468,10 +483,15 @@ struct BatchCtx {
         // engine 0: register-gather kernel (source rows placed by the bin layout); 2: LDS-gather kernel
         use_bins = (f->engine == 0 || f->engine == 3) && fe->bl_ok;
         pairs = f->engine == 0;  // engine 3: the single-tile kernel
-        want_mfma = (f->engine == 0 || f->engine == 2 || f->engine == 3) &&
+        int qrtf = 0;
+        quad = (f->engine == 0 || f->engine == 4) && fe->ql_ok && quad_shape(df, nrt, qrtf, nkb);
+        want_mfma = quad || (f->engine == 0 || f->engine == 2 || f->engine == 3) &&
                     (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
         // the LDS-gather kernel (engine 2) keeps host psi and host packing
         device_psi = f->engine != 2 && psi_lds_bytes(F->tgt.count, F->nsrc) <= 150 * 1024;
+        if (quad) {  // host psi, packed in the quad placement
+            use_bins = pairs = device_psi = false;
+        }
         return true;
     }
 };
@@ -546,8 +566,15 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             int umax = 0;
             for (size_t k = 0; k < it.chain_u.size(); k++) umax = std::max<int>(umax, it.chain_u[k]);
             const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
-            if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, sb.dps[i]) &&
-                mfma_supports_digits(sb.dps[i].D)) {
+            if (ctx.quad) {
+                if (quad_digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, sb.dps[i]) &&
+                    quad_supports_digits(sb.dps[i].D)) {
+                    it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
+                    pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), &ctx.fe->ql);
+                    sb.digit_ok[i] = 1;
+                }
+            } else if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, sb.dps[i]) &&
+                       mfma_supports_digits(sb.dps[i].D)) {
                 it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
                 if (!ctx.device_psi)
                     pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), ctx.use_bins ? &ctx.fe->bl : nullptr);
@@ -569,7 +596,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma; li++) sb.use_mfma = sb.digit_ok[sb.live[li]] != 0;
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
-    if (sb.use_mfma && !sb.use_bins && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
+    if (sb.use_mfma && !sb.use_bins && !ctx.quad && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
     sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;  // folded psi digits
     for (int li = 0; li < nlive && sb.use_pairs; li++)
         if (!mfma5_supports(df, sb.dps[sb.live[li]].D)) sb.use_pairs = false;
@@ -900,7 +927,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     uint64_t *storep = reinterpret_cast<uint64_t *>(db + sb.o_store);
     uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + sb.o_hbuf);
     int *errp = reinterpret_cast<int *>(db + sb.o_err);
-    const int mode = sb.use_mfma && sb.use_bins ? ctx.fam->launch : 0;
+    const int mode = sb.use_mfma && (sb.use_bins || ctx.quad) ? ctx.fam->launch : 0;
     int *queue = reinterpret_cast<int *>(db + sb.o_queue);
     // the reduction phases (and the combines between them) on stream `rs`
     auto reductions = [&](hipStream_t rs, bool timed) -> hipError_t {
@@ -930,7 +957,11 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                     const DevDigitItem *ditems = reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems);
                     const int Dg = L.key % 100;
                     const bool z32g = L.key >= 100;
-                    if (sb.use_pairs)
+                    if (ctx.quad)
+                        e = launch_reduce_quad(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
+                                               reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_qslots),
+                                               errp, Dg, mode > 0 ? 1 : 0, queue + li, rs);
+                    else if (sb.use_pairs)
                         e = launch_reduce_mfma5(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
                                                 errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
@@ -1437,7 +1468,7 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
             stats->reduce_launches += (int64_t)sb.launches.size();
             stats->fallbacks += sb.fallbacks;
             if (!sb.live.empty()) {
-                const int e = sb.use_mfma ? (sb.use_pairs ? 0 : (sb.use_bins ? 3 : 2)) : 1;
+                const int e = sb.use_mfma ? (ctx.quad ? 4 : (sb.use_pairs ? 0 : (sb.use_bins ? 3 : 2))) : 1;
                 // a sub-batch that fell back to the VALU kernel makes the call report it
                 if (stats->engine < 0 || e == 1) stats->engine = e;
             }

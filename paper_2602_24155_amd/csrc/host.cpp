@@ -968,6 +968,74 @@ bool bin_layout(const Family &fam, int nrt, BinLayout &bl) {
     return true;
 }
 
+bool quad_layout(const Family &fam, int nrt, int nrtf, BinLayout &bl) {
+    const int s = fam.g.count, nv = fam.nv;
+    if (nv != 4 || fam.nS != 4) return false;
+    bl.nbins = 2 * nrt;
+    bl.slot_src.assign((size_t)bl.nbins * 16, -1);
+    bl.slot.assign((size_t)bl.nbins * 16, 0);
+    // quads in accumulator order: full row tiles first (one output with all
+    // four sources per quad), then single row tiles (slot t: a one-source
+    // output of variable t)
+    int full_q = 0;
+    std::vector<int> single_q(nv, 0);
+    const int full_cap = nrtf * 2 * 4, single_cap = (nrt - nrtf) * 2 * 4;
+    for (int r = 0; r < s; r++) {
+        int members[4], cnt = 0;
+        for (int i = 0; i < nv; i++)
+            if (fam.gsrc[(size_t)r * nv + i] >= 0) members[cnt++] = i;
+        if (cnt == 0) continue;
+        if (cnt != 4 && cnt != 1) return false;
+        int qd, bin;
+        if (cnt == 4) {
+            if (full_q >= full_cap) return false;
+            qd = full_q++;
+            bin = qd / 4;
+        } else {
+            const int z = members[0];
+            if (single_q[z] >= single_cap) return false;
+            qd = single_q[z]++;
+            bin = 2 * nrtf + qd / 4;
+        }
+        for (int m = 0; m < cnt; m++) {
+            const int i = members[m], j = (qd % 4) * 4 + i;  // slot t of the quad is variable t
+            bl.slot_src[(size_t)bin * 16 + j] = fam.gsrc[(size_t)r * nv + i];
+            bl.slot[(size_t)bin * 16 + j] =
+                1u | ((uint32_t)i << 2) | ((uint32_t)fam.gw[(size_t)r * nv + i] << 5) | ((uint32_t)r << 16);
+        }
+    }
+    // every quad of a full row tile is a whole group or empty (marked r = 0xFFFF)
+    for (int qd = full_q; qd < full_cap; qd++) bl.slot[(size_t)(qd / 4) * 16 + (qd % 4) * 4] = 0xFFFFu << 16;
+    return true;
+}
+
+bool quad_digit_params(int p, int M, int T, int nv, u64 wtmax, DigitParams &dp) {
+    int e = 1;
+    while ((long long)std::llround(std::pow((double)p, e + 1)) <= 169) e++;
+    const long long B = (long long)std::llround(std::pow((double)p, e));
+    const int D = (M + e - 1) / e;
+    long double Q = 1;
+    for (int k = 0; k < D; k++) Q *= B;
+    if (Q >= std::ldexp(1.0L, 52)) return false;
+    const long long half = (B - 1) / 2;
+    // int32 MFMA accumulation: |Z_k| <= D T half^2
+    const long double Smax = (long double)D * T * half * half;
+    if (Smax >= std::ldexp(1.0L, 31) - 1) return false;
+    // weighted sums and carry sums: |t_k| <= (nv wtmax Smax + 1/2) B / (B - 1) < 2^48
+    const long double tmax = ((long double)nv * (long double)wtmax * Smax + 0.5L) * B / (long double)(B - 1);
+    if (tmax >= std::ldexp(1.0L, 48)) return false;
+    dp = DigitParams();
+    dp.e = e;
+    dp.B = (int)B;
+    dp.D = D;
+    dp.halfB = (int)half;
+    dp.Qp = (u64)Q;
+    dp.Bd = (double)B;
+    dp.Qd = (double)dp.Qp;
+    dp.invQ = 1.0 / dp.Qd;
+    return true;
+}
+
 void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out,
                      const BinLayout *bl) {
     const int D = dp.D, T = fam.tgt.count, half = (dp.B - 1) / 2;

@@ -162,6 +162,16 @@ struct BinLayout {
 };
 bool bin_layout(const Family &fam, int nrt, BinLayout &bl);
 
+// Row placement of the four-variable quad kernel (S = all): nrt row tiles, the
+// first nrtf of them full quads (the four source rows of one output, slot t =
+// variable t), the others single quads (four one-source outputs, slot t of
+// variable t); slot words as in BinLayout (end bit unused, r = 0xFFFF marks
+// an empty full quad).  False if the family's groups do not fit.
+bool quad_layout(const Family &fam, int nrt, int nrtf, BinLayout &bl);
+// Digits of the quad kernel: B = p^e <= 169, D = ceil(M / e), Q' = B^D < 2^52,
+// int32 position sums, carry sums below 2^48.
+bool quad_digit_params(int p, int M, int T, int nv, u64 wtmax, DigitParams &dp);
+
 // psi digits in v_mfma_i32_32x32x32_i8 A-fragment order:
 // out[(((rt*D + i)*nkb + kb)*64 + lane)*16 + j] = digit i of psi[32 rt + lane%32][32 kb + (lane/32)*16 + j]
 void pack_psi_digits(const Family &fam, const ItemSetup &it, const DigitParams &dp, int nrt, int nkb, int8_t *out,

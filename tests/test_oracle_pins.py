@@ -296,3 +296,24 @@ def test_paper_printed_facts():
             assert sizes == h[::-1] or sizes == h
         if "h02" in e:
             assert sizes[0] == e["h02"]
+
+
+def test_weil_check_with_repeated_roots():
+    """Q(T) with repeated reciprocal roots p, -p, p zeta (the algebraic classes of
+    a surface give such factors): the squarefree form of the Weil check accepts
+    it where plain numerical roots lose the precision, and still rejects a root
+    of the wrong modulus."""
+    from oracle.lpoly import squarefree_part, weil_root_check_squarefree
+    p = 13
+    a = [1]
+    for f in [[1, -p]] * 3 + [[1, p]] * 2 + [[1, 0, p * p]] + [[1, -p, p * p]] * 2 + [[1, p, p * p]] * 2 + \
+            [[1, -7, p * p]] * 2:
+        nxt = [0] * (len(a) + len(f) - 1)
+        for i, x in enumerate(a):
+            for j, y in enumerate(f):
+                nxt[i + j] += x * y
+        a = nxt
+    assert len(a) == 20 and len(squarefree_part(a)) == 11
+    assert weil_root_check_squarefree(a, p, 2)
+    bad = [x - (a[i - 1] if i else 0) for i, x in enumerate(a + [0])]  # times (1 - T)
+    assert not weil_root_check_squarefree(bad, p, 2)
