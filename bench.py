@@ -5,11 +5,15 @@ One step = one cr_frobenius_batch call over the whole batch: host setup,
 device reduction of every start term to pole n, device Griffiths-Dwork
 assembly, host unscaling and integer L-polynomials.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-cpu-baseline] [--no-legs]
 
-Prints one JSON line.  `roofline` describes the chain-reduction kernel (the
+Prints one JSON line.  `roofline` describes the reduction kernel (the
 dominant one), timed with HIP events on the stream it runs on; `cpu_baseline`
-times the CPU oracle on a bounded sample of the same workload.
+times the CPU oracle on a bounded sample of the same workload; `plain` is the
+per-hypersurface path on the same GPU (one cr_frobenius call per item, 64-bit
+VALU kernel, depth-first policy) and `learned` the batch under the learned
+policy (network trained on the GPU from plain-policy traces of other items).
 """
 import argparse
 import json
@@ -21,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
-KERNEL_NAMES = {0: "k_reduce_mfma5", 1: "k_reduce_chains", 2: "k_reduce_mfma", 3: "k_reduce_mfma4"}  # engine that ran
+KERNEL_NAMES = {0: "k_reduce_mfma5", 1: "k_reduce_chains", 2: "k_reduce_mfma", 3: "k_reduce_mfma4",
+                4: "k_reduce_quad"}  # engine that ran
 
 
 def measured_traffic(kernel, workload):
@@ -53,28 +58,105 @@ def _oracle_one(args):
     return 1
 
 
+def host_info():
+    """nproc, CPU model and clock of the host (from /proc/cpuinfo)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k == "model name" and "cpu_model" not in info:
+                info["cpu_model"] = v.strip()
+            elif k == "cpu MHz" and "cpu_mhz" not in info:
+                info["cpu_mhz"] = float(v)
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(name, items, budget_s=20.0):
     """The CPU oracle timed on the first items of the workload, on a pool of
-    host processes (one hypersurface per task) until ~budget_s of CPU work."""
+    host processes (one hypersurface per task, as many processes as the host
+    gives this job, at most 16) until ~budget_s of CPU work per process; at
+    least one item per process."""
     import multiprocessing as mp
     from paper_2602_24155_amd import workload
     w = workload.WORKLOADS[name]
-    cores = max(1, min(8, os.cpu_count() or 1))
+    cores = max(1, min(16, os.cpu_count() or 1))
     # calibrate on one item in this process
     t = time.perf_counter()
     _oracle_one((w.nvars, w.degree, items[0][0], items[0][1]))
     per = time.perf_counter() - t
-    n = max(cores, min(len(items), int(budget_s / max(per, 1e-3))))
+    n = max(cores, min(len(items), int(cores * budget_s / max(per, 1e-3))))
     n = min(n, len(items))
     sample = [(w.nvars, w.degree, p, c) for p, c in items[:n]]
     ctx = mp.get_context("fork")
     t = time.perf_counter()
-    with ctx.Pool(cores) as pool:
+    with ctx.Pool(min(cores, n)) as pool:
         done = sum(pool.map(_oracle_one, sample, chunksize=1))
     wall = time.perf_counter() - t
-    return {"value": done / wall, "unit": "frobenius_matrices/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d of the %d %s hypersurfaces, one per task on %d processes "
-                      "(exact-integer Python + plain-C oracle, %.1f s wall)" % (n, len(items), name, cores, wall)}
+    out = {"value": done / wall, "unit": "frobenius_matrices/s", "cores": min(cores, n), "kind": "oracle",
+           "sample": "first %d of the %d %s hypersurfaces, one per task on %d processes "
+                     "(exact-integer Python + plain-C oracle, %.1f s wall)" % (n, len(items), name, min(cores, n),
+                                                                                wall)}
+    out.update(host_info())
+    return out
+
+
+def plain_leg(C, w, items, sample, stream):
+    """The per-hypersurface path on the GPU: one cr_frobenius call per item
+    (64-bit VALU kernel, depth-first policy), over the first `sample` items."""
+    import torch
+    fam = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_DEPTH_FIRST, engine=C.ENGINE_VALU)
+    sub = items[:sample]
+    C.cr_frobenius(fam, sub[0][0], sub[0][1], stream=stream, want_scaled=False)  # warm up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    steps = 0
+    for p, c in sub:
+        steps += C.cr_frobenius(fam, p, c, stream=stream, want_scaled=False)["stats"].column_steps
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    return {"value": len(sub) / wall, "unit": "frobenius_matrices/s", "ms_per_matrix": wall / len(sub) * 1e3,
+            "matvecs_per_s": steps / wall, "sample": "first %d items, one cr_frobenius call each" % len(sub),
+            "engine": "k_reduce_chains (64-bit VALU)", "policy": "depth-first"}
+
+
+def learned_leg(C, w, fam0, items, primes, coeffs, stream, steps):
+    """The learned policy on the same batch: the network is trained on the GPU
+    (cr_mlp_train) from the plain p-chunk traces of 8 other items of the
+    workload, then the batch is reduced under CR_POLICY_LEARNED (judged by the
+    game cost against depth-first and p-chunk; the bits are unchanged)."""
+    import numpy as np
+    import torch
+    from paper_2602_24155_amd import workload
+    famc = C.family(w.nvars, w.degree, w.s_mask)
+    train = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(famc, p, c))
+             for j in range(w.count, w.count + 8)]
+    xs, ts = zip(*[C.cr_trace_policy(famc, p, c) for p, c in train])
+    x, t = np.concatenate(xs), np.concatenate(ts)
+    m = C.Mlp(seed=2)
+    t0 = time.perf_counter()
+    losses = m.train(x, t, epochs=8, batch=512, lr=2e-3, seed=4, stream=stream)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    fam = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_LEARNED, mlp=m, launch=fam0.launch)
+    C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st = res["stats"]
+    famp = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_P_CHUNK, launch=fam0.launch)
+    resp = C.cr_frobenius_batch(famp, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+    m.close()
+    return {"value": len(primes) / wall, "unit": "frobenius_matrices/s", "ms_per_step": wall * 1e3,
+            "column_steps": st.column_steps, "merged_terms": st.merged_terms, "fallbacks": st.fallbacks,
+            "p_chunk_column_steps": resp["stats"].column_steps, "p_chunk_merged_terms": resp["stats"].merged_terms,
+            "reduce_ms": st.reduce_ms, "p_chunk_reduce_ms": resp["stats"].reduce_ms,
+            "train_rows": int(x.shape[0]), "train_s": train_s, "train_loss": [float(losses[0]), float(losses[-1])]}
 
 
 def main():
@@ -84,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="quintic_curves_p31")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the plain per-hypersurface and learned-policy legs")
+    ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--policy", default="auto", choices=["auto", "depth-first", "p-chunk", "var-by-var"],
                     help="reduction policy; auto = the autotuner's choice (measured before the warmup)")
     ap.add_argument("--launch", default="auto", choices=["auto", "grid", "persistent", "graph"])
@@ -150,16 +234,23 @@ def main():
     value = len(items) * args.steps / wall
     _nco, s, b = C.cr_query_dims(w.nvars, w.degree)
     # algorithmic work of one step: column_steps products s x s . s mod p^M,
-    # priced as int8 MFMA ops with L balanced base-256 digits per residue
-    work = 0
+    # priced as int8 MFMA ops with L balanced base-256 digits per residue,
+    # item by item (the host plan gives each item's column steps)
+    work_p = {}
     for p in sorted(set(int(q) for q in primes)):
         _r, _N, M = C.cr_precision(fam, p)
         L = limbs_for(p ** M)
-        work_p = 2 * s * s * L * L
-        work += work_p * sum(1 for q in primes if q == p)
-    work_per_colstep = work / len(primes)
+        work_p[p] = 2 * s * s * L * L
+    work = None
+    if fam.policy != C.CR_POLICY_LEARNED:
+        cs = [C.cr_policy_cost(fam, int(p), c).column_steps for p, c in items]
+        if sum(cs) == st.column_steps:
+            work = sum(k * work_p[int(p)] for k, (p, _c) in zip(cs, items))
+    if work is None:  # the average over the batch's primes
+        work = st.column_steps * sum(work_p[int(q)] for q in primes) / len(primes)
+    work_per_colstep = work / st.column_steps
     red_s = tot["reduce_ms"] / 1e3 / args.steps
-    achieved = st.column_steps * work_per_colstep / red_s / 1e12
+    achieved = work / red_s / 1e12
     kname = KERNEL_NAMES.get(st.engine, "?") + ("_persistent" if st.engine == 3 and fam.launch > 0 else "")
     line = {
         "metric": "Frobenius matrices/sec (batched quintic curves, p=31) + modular matvecs/sec vs plain",
@@ -173,7 +264,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64 residues mod p^M (int8-limb / int32 exact products)",
-        "data": "synthetic: seeded random dense smooth curves, coefficients uniform in F_p",
+        "data": "synthetic: seeded random dense smooth hypersurfaces of the workload, coefficients uniform in F_p",
         "config": {"workload": args.workload, "count": len(items), "nvars": w.nvars, "degree": w.degree,
                    "primes": sorted(set(int(q) for q in primes)), "policy": pol_names[fam.policy],
                    "launch": launch_names[fam.launch], "autotune_ms_per_call": tuning,
@@ -188,6 +279,9 @@ def main():
                      "avg_launch_ms": tot["reduce_ms"] / args.steps / max(1, st.reduce_launches),
                      "work_per_column_step_int8_ops": work_per_colstep},
     }
+    if not args.no_legs:
+        line["plain"] = plain_leg(C, w, items, args.plain_sample, stream)
+        line["learned"] = learned_leg(C, w, fam, items, primes, coeffs, stream, max(1, args.steps // 2))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, items)
     print(json.dumps(line), flush=True)

@@ -91,6 +91,15 @@ __device__ __forceinline__ void choose_chunk_q(int d, int ndir, const int8_t *di
                 dir = t;
 }
 
+// A fragments (psi digits 0..D-1) of row tile rt, K-block kb; base = the
+// item's packed digits plus this lane's 16-byte offset.
+template <int D, int NKB>
+__device__ __forceinline__ void load_frags(const int8_t *base, int rt, int kb, v4i (&dst)[D]) {
+#pragma unroll
+    for (int i = 0; i < D; i++)
+        dst[i] = *reinterpret_cast<const v4i *>(base + (((size_t)rt * D + i) * NKB + kb) * 1024);
+}
+
 // Balanced base-B digits of x in [0, q) (q | Q'), written D planes apart.
 template <int D, int XS>
 __device__ __forceinline__ void put_digits_q(int8_t *xp, uint64_t x, uint64_t Qp, int B, int halfB) {
@@ -263,19 +272,26 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
         int8_t *Xn_c = Xn + c * XS;
         uint64_t *hrow = hbuf + (size_t)(tile.chain0 + c) * F;
 
+        // psi digit fragments one K-block ahead (and the next row tile's first
+        // block during the finish): one wave per SIMD has no other wave to hide
+        // the latency of the loads from L2
+        const int8_t *abase = it.apack + lane * 16;
+        v4i an[D];
+        if (wave < NRT) load_frags<D, NKB>(abase, wave, 0, an);
         for (int rt = wave; rt < NRT; rt += kQWaves) {
             v16i acc[D];
 #pragma unroll
             for (int k = 0; k < D; k++) acc[k] = v16i{0};
-            const int8_t *ap = it.apack + (size_t)rt * D * NKB * 1024 + lane * 16;
 #pragma unroll
             for (int kb = 0; kb < NKB; kb++) {
                 v4i xb[D], a[D];
 #pragma unroll
+                for (int i = 0; i < D; i++) a[i] = an[i];
+                if (kb + 1 < NKB) load_frags<D, NKB>(abase, rt, kb + 1, an);
+                else if (rt + kQWaves < NRT) load_frags<D, NKB>(abase, rt + kQWaves, 0, an);
+#pragma unroll
                 for (int j = 0; j < D; j++)
                     xb[j] = *reinterpret_cast<const v4i *>(Xc + (j * kQV + c) * XS + kb * 32 + half * 16);
-#pragma unroll
-                for (int i = 0; i < D; i++) a[i] = *reinterpret_cast<const v4i *>(ap + ((size_t)i * NKB + kb) * 1024);
 #pragma unroll
                 for (int i = 0; i < D; i++)
 #pragma unroll

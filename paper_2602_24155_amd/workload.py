@@ -9,7 +9,10 @@ consumer (the library's own validation, or a reference implementation in
 the tests): this module only produces numbers.
 
 The workloads stand in for the paper's random dense hypersurfaces
-(Tables 1-2 and Section 6); the paper's example files are not used.
+(Tables 1-2 and Section 6); the paper's example files are not used.  The
+sparse workload stands in for the six-term surfaces of Table 2 and the
+deformations of Method 2 (Section 6.1): the Fermat hypersurface plus
+`extra_terms` random monomials with random nonzero coefficients.
 """
 from dataclasses import dataclass
 from math import comb
@@ -28,6 +31,7 @@ class Workload:
     primes: tuple
     count: int
     s_mask: int = 0  # 0 = all variables (smooth case)
+    extra_terms: int = 0  # > 0: Fermat plus this many random monomials (sparse); 0: dense
 
     @property
     def ncoeff(self):
@@ -42,7 +46,23 @@ WORKLOADS = {
     "quartic_k3_mixed": Workload(3, "quartic_k3_mixed", 4, 4, (7, 11, 13), 64),
     "quintic_surfaces_mixed": Workload(4, "quintic_surfaces_mixed", 4, 5, (7, 11), 16),
     "cubic_fourfold_f7": Workload(5, "cubic_fourfold_f7", 6, 3, (7,), 1, s_mask=1 << 5),
+    "sparse_k3_mixed": Workload(7, "sparse_k3_mixed", 4, 4, (7, 11, 13), 64, extra_terms=2),
 }
+
+
+def monomial_exponents(nvars, degree):
+    """Degree-d exponent vectors in the library's order (lexicographically descending)."""
+    out = []
+
+    def rec(prefix, left, k):
+        if k == nvars - 1:
+            out.append(tuple(prefix + [left]))
+            return
+        for e in range(left, -1, -1):
+            rec(prefix + [e], left - e, k + 1)
+
+    rec([], degree, 0)
+    return out
 
 
 def stream(workload, j):
@@ -52,6 +72,17 @@ def stream(workload, j):
     p = int(w.primes[int(rng.integers(0, len(w.primes)))])
 
     def gen():
+        if w.extra_terms:
+            mons = monomial_exponents(w.nvars, w.degree)
+            pure = [k for k, m in enumerate(mons) if max(m) == w.degree]
+            other = [k for k, m in enumerate(mons) if max(m) < w.degree]
+            while True:
+                c = [0] * w.ncoeff
+                for k in pure:
+                    c[k] = 1
+                for k in rng.choice(other, size=w.extra_terms, replace=False):
+                    c[int(k)] = int(rng.integers(1, p))
+                yield c
         while True:
             yield [int(x) for x in rng.integers(0, p, size=w.ncoeff)]
 

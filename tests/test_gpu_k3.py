@@ -39,7 +39,7 @@ def _assert_golden(res, i, g):
 
 @pytest.mark.parametrize("policy", POLICIES)
 def test_goldens_quad_kernel(policy):
-    """The three stored random K3 surfaces (p = 11, 13, 7: digit counts 7, 7, 9)
+    """The twelve stored random K3 surfaces (four each at p = 7, 11, 13: digit counts 9, 7, 7)
     in one call on the quad kernel, bit for bit."""
     res = run_batch(4, 4, [(g["p"], g["coeffs"]) for g in GOLD], policy=policy)
     assert res["stats"].engine == C.ENGINE_QUAD and res["stats"].policy == policy

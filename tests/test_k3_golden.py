@@ -1,7 +1,8 @@
 """Random quartic K3 surfaces over F_7, F_11 and F_13: stored oracle results.
 
 tests/golden/k3_golden.json is written by tests/golden/make_k3_golden.py,
-which calls only oracle/ (about a minute per surface).  On the CPU the stored
+which calls only oracle/ (about a minute and a half per surface; four per
+prime, the first of each prime in workload order).  On the CPU the stored
 L-polynomials are checked against facts independent of the oracle (Weil
 bounds and the functional equation, #X(F_p) by brute force, the inputs being
 the workload's); on the GPU the library is compared with them bit for bit,
@@ -13,7 +14,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle.lpoly import point_counts_from_lpoly, weil_root_check
+from oracle.lpoly import point_counts_from_lpoly, weil_root_check_squarefree
 from oracle.poly import from_coeffs
 from oracle.pointcount import count_projective
 from paper_2602_24155_amd import crfrob as C
@@ -34,7 +35,8 @@ def test_golden_inputs_are_the_workload_items():
         # the stored candidate is one of the stream's candidates (the first smooth one)
         _p, gen = workload.stream("quartic_k3_mixed", it["j"])
         assert any(next(gen) == it["coeffs"] for _ in range(64))
-    assert sorted(it["p"] for it in golden()) == [7, 11, 13]
+    ps = [it["p"] for it in golden()]
+    assert all(ps.count(p) >= 4 for p in (7, 11, 13))
 
 
 def test_golden_lpolys_satisfy_weil_and_point_counts():
@@ -42,7 +44,7 @@ def test_golden_lpolys_satisfy_weil_and_point_counts():
         p = it["p"]
         a = [int(x) for x in it["lpoly"]]
         assert len(a) == 22 and a[0] == 1 and abs(a[21]) == p ** 21
-        assert weil_root_check(a, p, 2)
+        assert weil_root_check_squarefree(a, p, 2)
         f = {e: v % p for e, v in from_coeffs(4, 4, it["coeffs"]).items() if v % p}
         assert point_counts_from_lpoly(a, p, 3, 1) == [count_projective(f, 4, p, 1)]
 
@@ -50,8 +52,13 @@ def test_golden_lpolys_satisfy_weil_and_point_counts():
 def test_golden_lpolys_match_counts_over_f_p2():
     """#X(F_{p^2}) by brute force (per-line root counts over F_{p^2}) fixes the
     power sum s_2 of the Frobenius eigenvalues, a second independent
-    combination of the stored coefficients (a_1^2 - 2 a_2)."""
+    combination of the stored coefficients (a_1^2 - 2 a_2).  One surface per
+    prime (the count over F_{13^2} takes about 20 s)."""
+    seen = set()
     for it in golden():
+        if it["p"] in seen:
+            continue
+        seen.add(it["p"])
         p = it["p"]
         a = [int(x) for x in it["lpoly"]]
         f = {e: v % p for e, v in from_coeffs(4, 4, it["coeffs"]).items() if v % p}
