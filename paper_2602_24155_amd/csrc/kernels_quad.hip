@@ -93,11 +93,15 @@ __device__ __forceinline__ void choose_chunk_q(int d, int ndir, const int8_t *di
 
 // A fragments (psi digits 0..D-1) of row tile rt, K-block kb; base = the
 // item's packed digits plus this lane's 16-byte offset.
+// The loads go through a global-address-space pointer: as generic (flat)
+// loads they would also count on the LDS counter, and every wait for the
+// digit planes would then wait for the prefetch as well.
+typedef const __attribute__((address_space(1))) v4i gv4i;
+
 template <int D, int NKB>
 __device__ __forceinline__ void load_frags(const int8_t *base, int rt, int kb, v4i (&dst)[D]) {
 #pragma unroll
-    for (int i = 0; i < D; i++)
-        dst[i] = *reinterpret_cast<const v4i *>(base + (((size_t)rt * D + i) * NKB + kb) * 1024);
+    for (int i = 0; i < D; i++) dst[i] = *(gv4i *)(base + (((size_t)rt * D + i) * NKB + kb) * 1024);
 }
 
 // Balanced base-B digits of x in [0, q) (q | Q'), written D planes apart.
