@@ -48,6 +48,8 @@ hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, 
                                int pgrid, int *queue, hipStream_t stream);
 size_t psi_lds_bytes(int R, int C);
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream);
+hipError_t launch_psi_global(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, uint64_t *work,
+                             hipStream_t stream);
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
                            int nrt, int nkb, int T, int nsrc, int fold, hipStream_t stream);
 bool mfma4_supports(const DevFamily &fam, int D);
@@ -134,7 +136,7 @@ struct Arena {
 struct FamilyEntry {
     Family fam;
     std::vector<unsigned char> tables;  // packed device tables (host copy)
-    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src, off_qslots;
+    size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src, off_qslots, off_qslot_src;
     BinLayout bl;  // source-row placement for the register-gather MFMA kernel
     bool bl_ok = false;
     BinLayout ql;  // row placement of the four-variable quad kernel
@@ -198,6 +200,9 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         e->ql_ok = quad_shape(shape, qrt, qrtf, qkb) && quad_layout(F, qrt, qrtf, e->ql);
         if (!e->ql_ok) e->ql.slot.assign(16, 0);
         e->off_qslots = put(e->ql.slot.data(), e->ql.slot.size() * 4);
+        std::vector<int16_t> qs(e->ql.slot_src.begin(), e->ql.slot_src.end());
+        if (qs.empty()) qs.assign(16, -1);
+        e->off_qslot_src = put(qs.data(), qs.size() * 2);
     }
     auto *raw = e.get();
     g_families.emplace(key, std::move(e));
@@ -425,6 +430,7 @@ struct BatchCtx {
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
     bool quad = false;        // four-variable int8-digit MFMA kernel (k_reduce_quad)
+    bool psi_global = false;  // device psi with [J | I] in global memory (k_psi_global)
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
@@ -489,8 +495,10 @@ struct BatchCtx {
                     (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
         // the LDS-gather kernel (engine 2) keeps host psi and host packing
         device_psi = f->engine != 2 && psi_lds_bytes(F->tgt.count, F->nsrc) <= 150 * 1024;
-        if (quad) {  // host psi, packed in the quad placement
-            use_bins = pairs = device_psi = false;
+        if (quad) {  // device psi ([J | I] in global memory when it outgrows the LDS), digits in the quad placement
+            use_bins = pairs = false;
+            device_psi = true;
+            psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
         }
         return true;
     }
@@ -570,7 +578,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                 if (quad_digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, sb.dps[i]) &&
                     quad_supports_digits(sb.dps[i].D)) {
                     it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
-                    pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), &ctx.fe->ql);
+                    if (!ctx.device_psi)
+                        pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), &ctx.fe->ql);
                     sb.digit_ok[i] = 1;
                 }
             } else if (digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, 10, sb.dps[i]) &&
@@ -600,7 +609,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;  // folded psi digits
     for (int li = 0; li < nlive && sb.use_pairs; li++)
         if (!mfma5_supports(df, sb.dps[sb.live[li]].D)) sb.use_pairs = false;
-    if (sb.use_mfma && !sb.use_bins && ctx.device_psi) sb.use_mfma = false;  // device packing follows the bin layout
+    if (sb.use_mfma && !sb.use_bins && !ctx.quad && ctx.device_psi)
+        sb.use_mfma = false;  // device packing follows the bin layout (or the quad placement)
     if (!sb.use_mfma && ctx.device_psi && ctx.want_mfma) {
         // an item the MFMA kernel cannot take: the VALU kernel reads psi from k_psi directly
     }
@@ -911,7 +921,9 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         const DevItem *dv = reinterpret_cast<const DevItem *>(db + sb.o_items);
         if (he == hipSuccess && sb.use_mfma)
             he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
-                                 reinterpret_cast<const int16_t *>(db + sb.o_tables + ctx.fe->off_slot_src), ctx.nrt,
+                                 reinterpret_cast<const int16_t *>(
+                                     db + sb.o_tables + (ctx.quad ? ctx.fe->off_qslot_src : ctx.fe->off_slot_src)),
+                                 ctx.nrt,
                                  ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, sb.use_pairs ? 1 : 0, aux);
         (void)hipEventRecord(sb.epe, aux);
         if (he == hipSuccess) he = hipStreamWaitEvent(stream, sb.epe, 0);
@@ -1254,6 +1266,8 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     const size_t o_flags = take(4 * (size_t)count);
     const size_t h_end = off;
     const size_t o_psi = take(8 * psi_len * count);
+    // [J | I] of every item, for the global-memory elimination
+    const size_t o_work = ctx.psi_global ? take(8 * (size_t)F.tgt.count * (F.nsrc + F.tgt.count) * count) : 0;
     Arena &ar = *ctx.psi_arena;
     if (!ar.ensure(off, h_end)) {
         msg = ar.fixed ? "the right inverses of J_S need " + std::to_string(off) + " bytes of device memory; the "
@@ -1305,7 +1319,11 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     (void)hipEventCreate(&ctx.psi_done);
     if (he == hipSuccess) he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, aux);
     (void)hipEventRecord(ctx.psi_t0, aux);
-    if (he == hipSuccess)
+    if (he == hipSuccess && ctx.psi_global)
+        he = launch_psi_global(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
+                               reinterpret_cast<const int32_t *>(db + o_jtab),
+                               reinterpret_cast<uint64_t *>(db + o_work), aux);
+    else if (he == hipSuccess)
         he = launch_psi(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
                         reinterpret_cast<const int32_t *>(db + o_jtab), aux);
     if (he == hipSuccess)

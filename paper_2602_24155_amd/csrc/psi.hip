@@ -71,19 +71,20 @@ constexpr int kPsiWaves = kPsiThreads / 64;
 // pivot inverse (u64), the pivot marks of the columns (C int), 8 int of scratch
 size_t psi_lds_bytes(int R, int C) { return (size_t)R * (C + R) * 8 + (size_t)(R + 1) * 8 + (size_t)C * 4 + 32; }
 
-// J_S is built in LDS from the coefficients of f and the family table jtab:
-// entry (r, k) = c_e * w for jtab[r C + k] = (e << 8) | w, or 0 for -1.  An
-// item with q = 0 (rejected on the host) is skipped.
-__global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__ items, int R, int C,
-                                                     const int32_t *__restrict__ jtab) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const DevItem it = items[blockIdx.x];
-    if (it.q == 0) return;  // uniform over the workgroup
+// LDS of the global-memory form: everything but [J | I]
+size_t psi_small_lds_bytes(int R, int C) { return (size_t)(R + 1) * 8 + (size_t)C * 4 + 32; }
+
+// J_S is built from the coefficients of f and the family table jtab: entry
+// (r, k) = c_e * w for jtab[r C + k] = (e << 8) | w, or 0 for -1.  `a` holds
+// [J | I] (R x (C + R)), in LDS (k_psi) or in global memory (k_psi_global,
+// for families whose matrix does not fit the LDS); the pivot bookkeeping is
+// in LDS either way.
+__device__ static void psi_eliminate(const DevItem &it, int R, int C, const int32_t *__restrict__ jtab, uint64_t *a,
+                                     unsigned char *small) {
     const PMod md{it.q, it.mu, it.sbits};
     const uint32_t p = (uint32_t)it.p, two32p = (uint32_t)((1ull << 32) % p);
     const int W = C + R, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint64_t *a = reinterpret_cast<uint64_t *>(lds);
-    uint64_t *fcol = a + (size_t)R * W;
+    uint64_t *fcol = reinterpret_cast<uint64_t *>(small);
     uint64_t *shinv = fcol + R;
     int *used = reinterpret_cast<int *>(shinv + 1);
     int *sh = used + C;  // sh[0]: pivot column, sh[1]: failure
@@ -146,6 +147,27 @@ __global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__
     }
 }
 
+// An item with q = 0 (rejected on the host) is skipped.
+__global__ __launch_bounds__(kPsiThreads) void k_psi(const DevItem *__restrict__ items, int R, int C,
+                                                     const int32_t *__restrict__ jtab) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const DevItem it = items[blockIdx.x];
+    if (it.q == 0) return;  // uniform over the workgroup
+    uint64_t *a = reinterpret_cast<uint64_t *>(lds);
+    psi_eliminate(it, R, C, jtab, a, reinterpret_cast<unsigned char *>(a + (size_t)R * (C + R)));
+}
+
+// [J | I] of item i at work + i R (C + R) (global memory: 978 KB for quartic
+// K3 surfaces).  All of a workgroup's waves run on one CU, so its barriers
+// order their global reads and writes as they do for LDS.
+__global__ __launch_bounds__(kPsiThreads) void k_psi_global(const DevItem *__restrict__ items, int R, int C,
+                                                            const int32_t *__restrict__ jtab, uint64_t *work) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const DevItem it = items[blockIdx.x];
+    if (it.q == 0) return;
+    psi_eliminate(it, R, C, jtab, work + (size_t)blockIdx.x * R * (C + R), lds);
+}
+
 // Balanced base-B digits of psi in v_mfma_i32_32x32x32_i8 A-fragment order,
 // source rows placed by the bin layout:
 // apack[(((rt*D + i)*nkb + kb)*64 + lane)*16 + jj] = digit i of
@@ -196,6 +218,14 @@ hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int3
     hipError_t e = hipFuncSetAttribute((const void *)k_psi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_psi, dim3(nitems), dim3(kPsiThreads), lds, stream, items, R, C, jtab);
+    return hipGetLastError();
+}
+
+hipError_t launch_psi_global(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, uint64_t *work,
+                             hipStream_t stream) {
+    if (nitems == 0) return hipSuccess;
+    const size_t lds = psi_small_lds_bytes(R, C);
+    hipLaunchKernelGGL(k_psi_global, dim3(nitems), dim3(kPsiThreads), lds, stream, items, R, C, jtab, work);
     return hipGetLastError();
 }
 
