@@ -185,3 +185,23 @@ def test_single_entry_and_precision_overrides(engine):
             res["item_status"] = [one["status"]]
             o = frobenius(nv, d, p, c, **okw)
             assert_item_matches_oracle(res, 0, nv, d, p, c, oracle=o)
+
+
+def test_full_mixed_prime_batch():
+    """The whole 256-curve mixed-prime workload (p uniform over 11..47) in one
+    call: every item satisfies the Weil bound and the brute-force #C(F_p), and
+    the first curve of each prime is compared with the oracle bit for bit."""
+    items = workload_items("quintic_curves_mixed", range(256))
+    res = run_batch(3, 5, items, launch=C.LAUNCH_PERSISTENT)
+    assert res["status"] == C.CR_OK
+    first = {}
+    for i, (p, c) in enumerate(items):
+        a = res["lpoly"][i]
+        assert len(a) == 13 and a[0] == 1 and a[12] == p ** 6
+        assert weil_root_check(a, p, 1)
+        assert count_projective(from_coeffs(3, 5, c), 3, p, 1) == p + 1 + a[1]
+        first.setdefault(p, i)
+    assert sorted(first) == [11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47]
+    for p, i in sorted(first.items()):
+        print("mixed batch: oracle check of item %d (p = %d)" % (i, p), flush=True)
+        assert_item_matches_oracle(res, i, 3, 5, *items[i])
