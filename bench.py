@@ -209,10 +209,16 @@ def main():
         tu = C.cr_autotune(fam, primes, coeffs, trials=2, stream=stream)
         tuning = {"%s/%s" % (pol_names[k // 3], launch_names[k % 3]): round(tu.ms[k], 2)
                   for k in range(12) if tu.ms[k] > 0}
+        shape_names = ["auto/1", "auto/2", "single-tile/1", "single-tile/2", "lds-gather/1", "quad/1", "quad/2",
+                       "valu/1"]
+        tuning.update({"shape %s" % shape_names[k]: round(tu.shape_ms[k], 2) for k in range(8) if tu.shape_ms[k] > 0})
         if args.policy == "auto":
             fam.policy = tu.best_policy
         if args.launch == "auto":
             fam.launch = tu.best_launch
+        if args.policy == "auto" and args.launch == "auto":
+            fam.engine = tu.best_engine
+            fam.grid = tu.best_grid
     if args.policy != "auto":
         fam.policy = pol_names.index(args.policy)
     if args.launch != "auto":
@@ -267,7 +273,8 @@ def main():
         "data": "synthetic: seeded random dense smooth hypersurfaces of the workload, coefficients uniform in F_p",
         "config": {"workload": args.workload, "count": len(items), "nvars": w.nvars, "degree": w.degree,
                    "primes": sorted(set(int(q) for q in primes)), "policy": pol_names[fam.policy],
-                   "launch": launch_names[fam.launch], "autotune_ms_per_call": tuning,
+                   "launch": launch_names[fam.launch], "engine": fam.engine, "grid": fam.grid,
+                   "autotune_ms_per_call": tuning,
                    "start_blocks": st.start_blocks, "column_steps_per_step": st.column_steps,
                    "vectors_per_step": st.vectors, "merged_terms_per_step": st.merged_terms},
         "matvecs_per_s": st.column_steps / red_s,

@@ -117,6 +117,8 @@ typedef struct {
     int32_t n_series_m[6]; /* per pole order override of N_m (Proposition 2.1: the Frobenius
                          series of a column of pole m is truncated after N_m terms), entry m-1
                          for m = 1..n; 0 = n_series (or r + 1) */
+    int32_t grid;     /* persistent launches (launch >= 1): workgroups per CU of the grid, 1..4;
+                         0 = 1 */
 } cr_family;
 
 /* Per-call statistics (all counts are summed over the batch). */
@@ -305,19 +307,35 @@ cr_status cr_trace_policy(const cr_family *fam, int32_t p, const uint32_t *coeff
                           int32_t *rows);
 
 /* Autotuner of the batched launch (an extension of the method; the paper
- * parallelises only across CPU threads, Sections 5.1 and 7): runs the batch under every (policy, launch) pair -- policies
- * depth-first, p-chunk, var-by-var (and learned when fam->mlp is set), launch
- * modes 0, 1, 2 -- once to warm up and `trials` times timed (wall clock of
- * whole cr_frobenius_batch calls), and returns the fastest in best_policy /
- * best_launch.  ms[policy * 3 + launch] receives the mean time of each pair
- * (-1 when not run; room for 12 entries).  Every pair gives the same bits. */
+ * parallelises only across CPU threads, Sections 5.1 and 7).  Stage 1 runs
+ * the batch under every (policy, launch) pair -- policies depth-first,
+ * p-chunk, var-by-var (and learned when fam->mlp is set), launch modes 0, 1,
+ * 2 -- with fam's engine and grid; stage 2 runs the fastest pair under every
+ * kernel shape the family supports: engine (tile pairs, single tiles, LDS
+ * gather, quad, VALU) x persistent grid (1 or 2 workgroups per CU).  Each
+ * configuration runs once to warm up and `trials` times timed (wall clock of
+ * whole cr_frobenius_batch calls); configurations whose kernel differs from
+ * the one requested (cr_stats.engine) are not counted.  Every configuration
+ * gives the same bits.
+ *   ms[policy * 3 + launch]   stage-1 mean times (-1 when not run)
+ *   shape_ms[k]               stage-2 mean times for the shapes
+ *                             (engine, grid) = (0,1) (0,2) (3,1) (3,2) (2,1) (4,1) (4,2) (1,1)
+ * When a cache file is set (cr_autotune_cache), a result for the same family,
+ * batch (count and primes) and device is read from it instead of timing
+ * (from_cache = 1), and new results are appended to it. */
 typedef struct {
     int32_t best_policy, best_launch;
     double best_ms;
     double ms[12];
+    int32_t best_engine, best_grid;
+    int32_t from_cache;
+    double shape_ms[8];
 } cr_tuning;
 cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
                       int32_t trials, cr_tuning *out, void *hip_stream);
+/* File of persisted autotuner results (one line per tuned batch), or NULL to
+ * stop using one.  The path is copied. */
+cr_status cr_autotune_cache(const char *path);
 
 /*
  * Newton-polygon invariants of Q(T) (host only; Sections 1.2, 6.3, 6.4, 6.6).

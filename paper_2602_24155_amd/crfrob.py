@@ -17,21 +17,22 @@ CR_OK, CR_EINVAL, CR_ENOTPRIME, CR_EPRANGE, CR_ESINGULAR, CR_ENOT_S_SMOOTH, \
 CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNED = range(4)
 
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_residue_words", "cr_check_smooth",
-           "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_newton_polygon", "cr_policy_cost", "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights",
-           "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train", "cr_trace_policy", "cr_autotune", "cr_release",
-           "cr_last_error"]
+           "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_newton_polygon", "cr_policy_cost",
+           "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights", "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train",
+           "cr_trace_policy", "cr_autotune", "cr_autotune_cache", "cr_release", "cr_last_error"]
 
 
 class cr_family(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_int32), ("degree", ctypes.c_int32), ("s_mask", ctypes.c_uint32),
                 ("policy", ctypes.c_int32), ("r", ctypes.c_int32), ("n_series", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("launch", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("M", ctypes.c_int32), ("n_series_m", ctypes.c_int32 * 6)]
+                ("M", ctypes.c_int32), ("n_series_m", ctypes.c_int32 * 6), ("grid", ctypes.c_int32)]
 
 
 class cr_tuning(ctypes.Structure):
     _fields_ = [("best_policy", ctypes.c_int32), ("best_launch", ctypes.c_int32), ("best_ms", ctypes.c_double),
-                ("ms", ctypes.c_double * 12)]
+                ("ms", ctypes.c_double * 12), ("best_engine", ctypes.c_int32), ("best_grid", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("shape_ms", ctypes.c_double * 8)]
 
 
 class cr_train_opts(ctypes.Structure):
@@ -103,6 +104,7 @@ def lib():
         L.cr_mlp_train.argtypes = [vp, i32, P(f32), P(f32), P(cr_train_opts), P(f32), vp]
         L.cr_trace_policy.argtypes = [P(cr_family), i32, P(u32), i32, P(f32), P(f32), P(i32)]
         L.cr_autotune.argtypes = [P(cr_family), i32, P(i32), P(u32), i32, P(cr_tuning), vp]
+        L.cr_autotune_cache.argtypes = [ctypes.c_char_p]
         L.cr_release.argtypes = []
         L.cr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -128,11 +130,12 @@ LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2
 
 
 def family(nvars, degree, s_mask=0, policy=CR_POLICY_DEPTH_FIRST, r=0, n_series=0, engine=ENGINE_AUTO, mlp=None,
-           launch=LAUNCH_GRID, M=0, n_series_m=None):
-    """n_series_m: series orders N_m of pole orders m = 1..n (0 entries = n_series)."""
+           launch=LAUNCH_GRID, M=0, n_series_m=None, grid=0):
+    """n_series_m: series orders N_m of pole orders m = 1..n (0 entries = n_series);
+    grid: workgroups per CU of persistent launches (0 = 1)."""
     nm = list(n_series_m or []) + [0] * (6 - len(n_series_m or []))
     return cr_family(nvars, degree, s_mask, policy, r, n_series, engine, launch,
-                     mlp.handle if mlp is not None else None, M, (ctypes.c_int32 * 6)(*nm))
+                     mlp.handle if mlp is not None else None, M, (ctypes.c_int32 * 6)(*nm), grid)
 
 
 def cr_query_dims(nvars, degree):
@@ -339,6 +342,11 @@ def cr_autotune(fam, primes, coeffs, trials=2, stream=None):
     _check(lib().cr_autotune(ctypes.byref(fam), primes.shape[0], _ptr(primes, ctypes.c_int32),
                              _ptr(co, ctypes.c_uint32), trials, ctypes.byref(out), ctypes.c_void_p(stream or 0)))
     return out
+
+
+def cr_autotune_cache(path):
+    """Persist autotuner results in `path` (None: stop)."""
+    _check(lib().cr_autotune_cache(path.encode() if path is not None else None))
 
 
 def cr_release():

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <functional>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -57,8 +58,8 @@ bool quad_shape(const DevFamily &fam, int &nrt, int &nrtf, int &nkb);
 bool quad_supports_digits(int D);
 hipError_t launch_reduce_quad(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
-                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, int pgrid,
-                              int *queue, hipStream_t stream);
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
+                              hipStream_t stream);
 }  // namespace crf
 
 using namespace crf;
@@ -323,6 +324,10 @@ bool check_family(const cr_family *fam, std::string &err) {
     }
     if (fam->launch < 0 || fam->launch > 2) {
         err = "unknown launch mode";
+        return false;
+    }
+    if (fam->grid < 0 || fam->grid > 4) {
+        err = "persistent grid must be 0..4 workgroups per CU";
         return false;
     }
     if (fam->policy != CR_POLICY_DEPTH_FIRST && fam->engine == 2) {
@@ -633,7 +638,8 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     // ---- vectors of every phase in launch order (phase, digit group, item), tiles of ct vectors of one item
     std::vector<int> gkey(nlive, 0), dvals;
     for (int li = 0; li < nlive; li++)
-        if (sb.use_mfma) gkey[li] = sb.dps[sb.live[li]].D + 100 * sb.dps[sb.live[li]].z32;
+        if (sb.use_mfma && !ctx.quad)  // the quad kernel takes every digit count in one launch
+            gkey[li] = sb.dps[sb.live[li]].D + 100 * sb.dps[sb.live[li]].z32;
     dvals = gkey;
     std::sort(dvals.begin(), dvals.end());
     dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());
@@ -940,6 +946,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + sb.o_hbuf);
     int *errp = reinterpret_cast<int *>(db + sb.o_err);
     const int mode = sb.use_mfma && (sb.use_bins || ctx.quad) ? ctx.fam->launch : 0;
+    const int pgrid = mode > 0 ? std::max(1, ctx.fam->grid) : 0;  // persistent: workgroups per CU
     int *queue = reinterpret_cast<int *>(db + sb.o_queue);
     // the reduction phases (and the combines between them) on stream `rs`
     auto reductions = [&](hipStream_t rs, bool timed) -> hipError_t {
@@ -972,15 +979,15 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                     if (ctx.quad)
                         e = launch_reduce_quad(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_qslots),
-                                               errp, Dg, mode > 0 ? 1 : 0, queue + li, rs);
+                                               errp, pgrid, queue + li, rs);
                     else if (sb.use_pairs)
                         e = launch_reduce_mfma5(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
-                                                errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
+                                                errp, Dg, z32g, pgrid, queue + li, rs);
                     else if (sb.use_bins)
                         e = launch_reduce_mfma4(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
-                                                errp, Dg, z32g, mode > 0 ? 1 : 0, queue + li, rs);
+                                                errp, Dg, z32g, pgrid, queue + li, rs);
                     else
                         e = launch_reduce_mfma(df, ditems, gt, L.ntiles, cu, cgp, cp, hb64, errp, Dg, rs);
                 } else {
@@ -992,7 +999,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     };
     if (he == hipSuccess && mode == 2) {
         // signature of every launch parameter: an identical one replays the cached graph
-        std::string sig = std::to_string((uintptr_t)db) + ":" + std::to_string(sb.nphase);
+        std::string sig = std::to_string((uintptr_t)db) + ":" + std::to_string(sb.nphase) + ":" + std::to_string(pgrid);
         for (auto &L : sb.launches)
             sig += "|" + std::to_string(L.phase) + "," + std::to_string(L.key) + "," + std::to_string(L.tile0) + "," +
                    std::to_string(L.ntiles);
@@ -1534,10 +1541,76 @@ cr_status cr_frobenius(const cr_family *fam, int32_t p, const uint32_t *coeffs, 
     return st != CR_OK ? st : (cr_status)st_item;
 }
 
+}  // extern "C"
+
+namespace {
+
+std::string g_tune_cache;  // file of persisted autotuner results ("" = none)
+
+// Key of a tuned batch: family, count, the multiset of primes, device.
+std::string tune_key(const cr_family *fam, int32_t count, const int32_t *primes) {
+    std::map<int, int> hist;
+    for (int i = 0; i < count; i++) hist[primes[i]]++;
+    std::string k = std::to_string(fam->nvars) + "," + std::to_string(fam->degree) + "," + std::to_string(fam->s_mask) +
+                    "," + std::to_string(fam->r) + "," + std::to_string(fam->n_series) + "," + std::to_string(fam->M) +
+                    ",n=" + std::to_string(count) + ",p=";
+    for (auto &h : hist) k += std::to_string(h.first) + "x" + std::to_string(h.second) + ".";
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        k += std::string(",") + prop.gcnArchName + "/" + std::to_string(prop.multiProcessorCount);
+    for (char &ch : k)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    return k;
+}
+
+bool tune_lookup(const std::string &key, cr_tuning *out) {
+    if (g_tune_cache.empty()) return false;
+    FILE *f = std::fopen(g_tune_cache.c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[768];
+        int pol, lm, eng, grid;
+        double ms;
+        if (std::sscanf(line, "%767s %d %d %d %d %lf", k, &pol, &lm, &eng, &grid, &ms) == 6 && key == k) {
+            out->best_policy = pol;  // the last entry for a key wins
+            out->best_launch = lm;
+            out->best_engine = eng;
+            out->best_grid = grid;
+            out->best_ms = ms;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const std::string &key, const cr_tuning *t) {
+    if (g_tune_cache.empty()) return;
+    FILE *f = std::fopen(g_tune_cache.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %.4f\n", key.c_str(), t->best_policy, t->best_launch, t->best_engine, t->best_grid,
+                 t->best_ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+cr_status cr_autotune_cache(const char *path) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    g_tune_cache = path ? path : "";
+    return CR_OK;
+}
+
 cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes, const uint32_t *coeffs,
                       int32_t trials, cr_tuning *out, void *hip_stream) {
     std::string err;
-    if (!check_family(fam, err) || !out || count <= 0 || trials < 1) return fail(CR_EINVAL, err.empty() ? "bad arguments" : err);
+    if (!check_family(fam, err) || !out || count <= 0 || trials < 1 || !primes || !coeffs)
+        return fail(CR_EINVAL, err.empty() ? "bad arguments" : err);
     int32_t nco, s_dim, b;
     cr_query_dims(fam->nvars, fam->degree, &nco, &s_dim, &b);
     std::vector<uint64_t> frob((size_t)count * b * b);
@@ -1545,7 +1618,31 @@ cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes
     std::vector<int64_t> lp((size_t)count * (b + 1) * 4);
     std::memset(out, 0, sizeof(*out));
     for (double &x : out->ms) x = -1;
+    for (double &x : out->shape_ms) x = -1;
     out->best_ms = -1;
+    std::string key;
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        key = tune_key(fam, count, primes);
+        if (tune_lookup(key, out)) {
+            out->from_cache = 1;
+            return CR_OK;
+        }
+    }
+    // mean wall time of `trials` calls after one warm-up call; -1 if a call
+    // fails, or (for an explicit engine) ran another kernel than the one asked for
+    auto time_cfg = [&](const cr_family &f) -> double {
+        double tot = 0;
+        for (int r = 0; r <= trials; r++) {
+            cr_stats st{};
+            auto t0 = std::chrono::steady_clock::now();
+            cr_status cs = cr_frobenius_batch(&f, count, primes, coeffs, frob.data(), nullptr, pole.data(),
+                                              prec.data(), lp.data(), ist.data(), &st, hip_stream);
+            if (cs != CR_OK || (f.engine != 0 && st.engine != f.engine)) return -1;
+            if (r > 0) tot += ms_since(t0);
+        }
+        return tot / trials;
+    };
     std::vector<int> pols = {CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR};
     if (fam->mlp) pols.push_back(CR_POLICY_LEARNED);
     for (int pol : pols)
@@ -1554,25 +1651,40 @@ cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes
             f.policy = pol;
             f.launch = lm;
             if (!check_family(&f, err)) continue;
-            double tot = 0;
-            bool ok = true;
-            for (int r = 0; r <= trials && ok; r++) {
-                auto t0 = std::chrono::steady_clock::now();
-                cr_status st = cr_frobenius_batch(&f, count, primes, coeffs, frob.data(), nullptr, pole.data(),
-                                                  prec.data(), lp.data(), ist.data(), nullptr, hip_stream);
-                if (st != CR_OK) ok = false;
-                if (r > 0) tot += ms_since(t0);
-            }
-            if (!ok) continue;
-            const double ms = tot / trials;
+            const double ms = time_cfg(f);
+            if (ms < 0) continue;
             out->ms[pol * 3 + lm] = ms;
             if (out->best_ms < 0 || ms < out->best_ms) {
                 out->best_ms = ms;
                 out->best_policy = pol;
                 out->best_launch = lm;
+                out->best_engine = fam->engine;
+                out->best_grid = std::max(1, fam->grid);
             }
         }
     if (out->best_ms < 0) return fail(CR_EINVAL, "no configuration ran: " + g_err);
+    // kernel shapes for the best (policy, launch)
+    static const int shapes[8][2] = {{0, 1}, {0, 2}, {3, 1}, {3, 2}, {2, 1}, {4, 1}, {4, 2}, {1, 1}};
+    for (int k = 0; k < 8; k++) {
+        cr_family f = *fam;
+        f.policy = out->best_policy;
+        f.launch = out->best_launch;
+        f.engine = shapes[k][0];
+        f.grid = shapes[k][1];
+        if (f.launch == 0 && f.grid > 1) continue;  // the grid only shapes persistent launches
+        if (!check_family(&f, err)) continue;
+        const double ms = time_cfg(f);
+        out->shape_ms[k] = ms;
+        if (ms >= 0 && ms < out->best_ms) {
+            out->best_ms = ms;
+            out->best_engine = f.engine;
+            out->best_grid = f.grid;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        tune_store(key, out);
+    }
     return CR_OK;
 }
 

@@ -173,7 +173,9 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
     constexpr int XS = Sh::XS, XB = Sh::XB, NT = 64 * kQWaves;
     const int s = fam.s, F = fam.F;
     const DevDigitItem it = items[tile.item];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index is uniform over the wave: in a scalar register, every
+    // row-tile offset below is scalar arithmetic
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int c = lane & 31, half = lane >> 5;
     const int nch = tile.count;
 
@@ -358,16 +360,36 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
     }
 }
 
+// One tile with the digit count of its item: DLO or DHI (the hypersurfaces
+// of one call may have different primes, hence different digit counts; one
+// launch takes the tiles of all of them).
+template <int NRT, int NRTF, int NKB, int DLO, int DHI>
+__device__ __forceinline__ void quad_tile_any(const DevFamily &fam, const DevTile &tile,
+                                              const DevDigitItem *__restrict__ items, const int16_t *__restrict__ cu,
+                                              const int32_t *__restrict__ cg, const int32_t *__restrict__ cpole,
+                                              const DevVec *__restrict__ vx, uint64_t *__restrict__ store,
+                                              uint64_t *__restrict__ hbuf, int &bad, int8_t *Xbuf,
+                                              const int16_t *colmapL, const int8_t *dirsL, const int8_t *finUL,
+                                              const uint32_t *slotL) {
+    const int D = __builtin_amdgcn_readfirstlane(items[tile.item].D);
+    if (D == DLO)
+        quad_tile<NRT, NRTF, NKB, DLO>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL, dirsL,
+                                       finUL, slotL);
+    else
+        quad_tile<NRT, NRTF, NKB, DHI>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL, dirsL,
+                                       finUL, slotL);
+}
+
 // One workgroup per tile (queue == nullptr) or a persistent grid draining the
 // tile list through the counter *queue (zero at launch; every workgroup
-// leaves once the counter passes ntiles).
-template <int NRT, int NRTF, int NKB, int D>
+// leaves once the counter passes ntiles).  The LDS is laid out for DHI.
+template <int NRT, int NRTF, int NKB, int DLO, int DHI>
 __global__ __launch_bounds__(64 * kQWaves) void k_reduce_quad(
     DevFamily fam, const DevDigitItem *__restrict__ items, const DevTile *__restrict__ tiles, int ntiles,
     int *__restrict__ queue, const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
     const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx, uint64_t *__restrict__ store,
     uint64_t *__restrict__ hbuf, const uint32_t *__restrict__ slots, int *__restrict__ err) {
-    using Sh = QuadShape<NRT, NKB, D>;
+    using Sh = QuadShape<NRT, NKB, DHI>;
     extern __shared__ __align__(16) unsigned char ldsq[];
     int8_t *Xbuf = reinterpret_cast<int8_t *>(ldsq);
     int16_t *colmapL = reinterpret_cast<int16_t *>(ldsq + 2 * (size_t)Sh::XB);
@@ -384,29 +406,29 @@ __global__ __launch_bounds__(64 * kQWaves) void k_reduce_quad(
     int bad = 0;
     if (!queue) {
         if (blockIdx.x < (unsigned)ntiles)
-            quad_tile<NRT, NRTF, NKB, D>(fam, tiles[blockIdx.x], items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf,
-                                         colmapL, dirsL, finUL, slotL);
+            quad_tile_any<NRT, NRTF, NKB, DLO, DHI>(fam, tiles[blockIdx.x], items, cu, cg, cpole, vx, store, hbuf, bad,
+                                                    Xbuf, colmapL, dirsL, finUL, slotL);
     } else {
         for (;;) {
             if (tid == 0) next = atomicAdd(queue, 1);
             __syncthreads();
-            const int ti = next;
+            const int ti = __builtin_amdgcn_readfirstlane(next);  // uniform: the tile's fields load into SGPRs
             __syncthreads();  // every thread has read `next` before it is overwritten
             if (ti >= ntiles) break;
-            quad_tile<NRT, NRTF, NKB, D>(fam, tiles[ti], items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL,
-                                         dirsL, finUL, slotL);
+            quad_tile_any<NRT, NRTF, NKB, DLO, DHI>(fam, tiles[ti], items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf,
+                                                    colmapL, dirsL, finUL, slotL);
         }
     }
     if (bad) atomicOr(err, bad);
 }
 
-template <int R, int RF, int KB, int DD>
+template <int R, int RF, int KB, int DL, int DH>
 hipError_t launch_quad_one(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                            const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
                            uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
                            hipStream_t stream) {
-    constexpr size_t lds = QuadShape<R, KB, DD>::lds;
-    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_quad<R, RF, KB, DD>,
+    constexpr size_t lds = QuadShape<R, KB, DH>::lds;
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_quad<R, RF, KB, DL, DH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int grid = ntiles;
@@ -416,7 +438,7 @@ hipError_t launch_quad_one(const DevFamily &fam, const DevDigitItem *items, cons
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         grid = std::min(ntiles, std::max(1, cus) * pgrid);
     }
-    hipLaunchKernelGGL((k_reduce_quad<R, RF, KB, DD>), dim3(grid), dim3(64 * kQWaves), lds, stream, fam, items, tiles,
+    hipLaunchKernelGGL((k_reduce_quad<R, RF, KB, DL, DH>), dim3(grid), dim3(64 * kQWaves), lds, stream, fam, items, tiles,
                        ntiles, pgrid > 0 ? queue : nullptr, cu, cg, cpole, vx, store, hbuf, slots, err);
     return hipGetLastError();
 }
@@ -427,9 +449,6 @@ hipError_t launch_quad_one(const DevFamily &fam, const DevDigitItem *items, cons
 // them full quads), nkb K-blocks.  Quartic K3 surfaces: 11, 7, 7.
 bool quad_shape(const DevFamily &fam, int &nrt, int &nrtf, int &nkb) {
     nkb = (fam.T + 31) / 32;
-    // full quads hold the outputs with four sources, single quads four one-source outputs
-    const int nfull = (fam.nsrc - 112) / 4;  // set from the slot table on the host; see quad_layout
-    (void)nfull;
     nrt = 11;
     nrtf = 7;
     return fam.nv == 4 && fam.smask == 0xFu && fam.s == 220 && fam.T == 220 && fam.nsrc == 336 &&
@@ -438,24 +457,17 @@ bool quad_shape(const DevFamily &fam, int &nrt, int &nrtf, int &nkb) {
 
 bool quad_supports_digits(int D) { return D == 7 || D == 9; }
 
-size_t quad_lds_bytes(int D) {
-    return D == 7 ? QuadShape<11, 7, 7>::lds : QuadShape<11, 7, 9>::lds;
-}
-
+// One launch for the tiles of every item, whatever its digit count (each
+// item's DevDigitItem.D is 7 or 9; quad_supports_digits is checked on the host).
 hipError_t launch_reduce_quad(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
-                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, int pgrid,
-                              int *queue, hipStream_t stream) {
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
+                              hipStream_t stream) {
     if (ntiles == 0) return hipSuccess;
     int nrt, nrtf, nkb;
     if (!quad_shape(fam, nrt, nrtf, nkb) || nkb != 7) return hipErrorInvalidValue;
-    if (D == 7)
-        return launch_quad_one<11, 7, 7, 7>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,
-                                            pgrid, queue, stream);
-    if (D == 9)
-        return launch_quad_one<11, 7, 7, 9>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,
-                                            pgrid, queue, stream);
-    return hipErrorInvalidValue;
+    return launch_quad_one<11, 7, 7, 7, 9>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, err,
+                                           pgrid, queue, stream);
 }
 
 }  // namespace crf

@@ -49,13 +49,42 @@ def test_full_size_launch_modes_agree():
             assert np.array_equal(res["scaled"], base["scaled"]) and res["lpoly"] == base["lpoly"], (launch, rep)
 
 
-def test_autotune_small_batch():
+def test_autotune_small_batch(tmp_path):
+    """Stage 1 times every (policy, launch) pair, stage 2 the kernel shapes
+    (engine x persistent grid) of the best pair; the best configuration gives
+    the same bits; a cache file returns the same choice without timing."""
     items = workload_items("quintic_curves_p31", range(8))
+    primes, coeffs = [p for p, _ in items], [c for _, c in items]
     fam = C.family(3, 5)
-    tu = C.cr_autotune(fam, [p for p, _ in items], [c for _, c in items], trials=1)
-    ms = list(tu.ms)
-    assert all(ms[pol * 3 + lm] > 0 for pol in range(3) for lm in range(3))
-    assert tu.best_ms == ms[tu.best_policy * 3 + tu.best_launch] == min(x for x in ms if x > 0)
-    res = run_batch(3, 5, items, policy=tu.best_policy, launch=tu.best_launch)
+    cache = str(tmp_path / "tune.txt")
+    C.cr_autotune_cache(cache)
+    try:
+        tu = C.cr_autotune(fam, primes, coeffs, trials=1)
+        assert tu.from_cache == 0
+        ms = list(tu.ms)
+        assert all(ms[pol * 3 + lm] > 0 for pol in range(3) for lm in range(3))
+        shapes = list(tu.shape_ms)
+        # plane quintics: auto (tile pairs), single tiles, LDS gather and VALU run; the quad kernel does not
+        assert shapes[0] > 0 and shapes[2] > 0 and shapes[7] > 0 and shapes[5] < 0 and shapes[6] < 0
+        assert tu.best_ms == min(x for x in ms + shapes if x > 0)
+        res = run_batch(3, 5, items, policy=tu.best_policy, launch=tu.best_launch, engine=tu.best_engine,
+                        grid=tu.best_grid)
+        base = run_batch(3, 5, items)
+        assert np.array_equal(res["scaled"], base["scaled"]) and res["lpoly"] == base["lpoly"]
+        again = C.cr_autotune(fam, primes, coeffs, trials=1)
+        assert again.from_cache == 1
+        assert (again.best_policy, again.best_launch, again.best_engine, again.best_grid) == \
+            (tu.best_policy, tu.best_launch, tu.best_engine, tu.best_grid)
+        assert open(cache).read().count("\n") == 1
+    finally:
+        C.cr_autotune_cache(None)
+
+
+@pytest.mark.parametrize("grid", [1, 2])
+def test_persistent_grid_sizes(grid):
+    items = workload_items("quintic_curves_mixed", range(6))
     base = run_batch(3, 5, items)
-    assert np.array_equal(res["scaled"], base["scaled"])
+    for engine in (C.ENGINE_AUTO, C.ENGINE_MFMA_SINGLE):
+        res = run_batch(3, 5, items, launch=C.LAUNCH_PERSISTENT, grid=grid, engine=engine)
+        assert res["stats"].engine == engine
+        assert np.array_equal(res["scaled"], base["scaled"]) and res["lpoly"] == base["lpoly"]

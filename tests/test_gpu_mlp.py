@@ -111,3 +111,44 @@ def test_learned_policy_without_model_is_an_error():
     res = C.cr_frobenius_batch(C.family(3, 4, policy=C.CR_POLICY_LEARNED), [items[0][0]], [items[0][1]],
                                raise_on_error=False)
     assert res["status"] == C.CR_EINVAL
+
+
+def test_network_trained_on_curves_and_k3_surfaces():
+    """One network trained on the GPU from the plain p-chunk traces of the three
+    dense families (a quartic curve over F_7, quintic curves, quartic K3
+    surfaces; held-out items), then used on the stored K3 goldens: the judge
+    keeps learned plans, they need fewer column steps than p-chunk, and the
+    bits equal the oracle's."""
+    import json
+    import os
+    from paper_2602_24155_amd import workload
+    xs, ts = [], []
+    for nv, d, name, js in [(3, 4, "quartic_curve_f7", [0]), (3, 5, "quintic_curves_mixed", range(100, 104))]:
+        for p, c in workload_items(name, js):
+            x, t = C.cr_trace_policy(C.family(nv, d), p, c)
+            xs.append(x)
+            ts.append(t)
+    w = workload.WORKLOADS["quartic_k3_mixed"]
+    fam4 = C.family(4, 4)
+    for j in (40, 41):  # not among the goldens
+        p, c = workload.first_accepted(w, j, lambda p_, c_: C.cr_check_smooth(fam4, p_, c_))
+        x, t = C.cr_trace_policy(fam4, p, c)
+        xs.append(x)
+        ts.append(t)
+    x, t = np.concatenate(xs), np.concatenate(ts)
+    m = C.Mlp(seed=7)
+    losses = m.train(x, t, epochs=6, batch=1024, lr=2e-3, seed=3)
+    assert losses[-1] < 0.7 * losses[0]
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "k3_golden.json")))["items"][:6]
+    primes, coeffs = [g["p"] for g in gold], [g["coeffs"] for g in gold]
+    res = C.cr_frobenius_batch(C.family(4, 4, policy=C.CR_POLICY_LEARNED, mlp=m), primes, coeffs)
+    st = res["stats"]
+    assert st.policy == C.CR_POLICY_LEARNED and st.engine == C.ENGINE_QUAD and st.fallbacks < len(gold)
+    pc = [C.cr_policy_cost(C.family(4, 4, policy=C.CR_POLICY_P_CHUNK), p, c) for p, c in zip(primes, coeffs)]
+    print("K3 column steps: learned %d, p-chunk %d (fallbacks %d of %d)"
+          % (st.column_steps, sum(x.column_steps for x in pc), st.fallbacks, len(gold)), flush=True)
+    assert st.column_steps + st.merged_terms / 8.0 < sum(x.column_steps + x.merged_terms / 8.0 for x in pc)
+    for i, g in enumerate(gold):
+        assert [[int(v) for v in row] for row in res["scaled"][i]] == [[int(v) for v in row] for row in g["scaled"]]
+        assert res["lpoly"][i] == [int(a) for a in g["lpoly"]]
+    m.close()
