@@ -44,7 +44,9 @@ extern "C" {
 
 typedef enum {
     CR_OK = 0,
-    CR_EINVAL = 1,        /* bad sizes / null pointers / unsupported nvars, degree */
+    CR_EINVAL = 1,        /* bad sizes / null pointers / unsupported nvars, degree, or a family
+                             with no device path (a right inverse beyond 2^20 entries and no
+                             MFMA kernel: cubic threefolds and fourfolds) */
     CR_ENOTPRIME = 2,     /* p is not prime */
     CR_EPRANGE = 3,       /* need 7 <= p < 50, p > n, p not dividing d */
     CR_ESINGULAR = 4,     /* f mod p is singular (Jacobian criterion) */
@@ -373,6 +375,25 @@ typedef struct {
     int32_t domino_num, domino_den;
 } cr_newton;
 cr_status cr_newton_polygon(int32_t nvars, int32_t degree, int32_t p, const int64_t *lpoly, cr_newton *out);
+
+/* Device memory hook: where the batch workspaces and the cr_mlp handles get
+ * their device memory (for instance a framework's caching allocator); without
+ * one, hipMalloc / hipFree.  alloc(bytes, ctx) returns `bytes` of device
+ * memory on the current device, 256-byte aligned, or NULL (the call then
+ * fails with CR_ENOMEM); free_(ptr, ctx) takes back a block alloc returned.
+ * Both NULL restores hipMalloc; exactly one NULL is CR_EINVAL.  The setting
+ * is process-wide.  Installing it frees the library's cached workspaces (the
+ * next call allocates through the new hook); every block is returned through
+ * the hook that allocated it, and only after the device has finished all work
+ * (the library waits for the device before calling free_), so a hook may hand
+ * the block out again at once.  The hooks run on the thread that calls the
+ * library, inside cr_frobenius_batch, cr_frobenius, cr_autotune, cr_release,
+ * cr_set_allocator and the cr_mlp_* calls, and must not call back into the
+ * library.  Pinned host staging still comes from hipHostMalloc, and
+ * cr_frobenius_batch_noalloc allocates nothing through either. */
+typedef void *(*cr_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*cr_free_fn)(void *ptr, void *ctx);
+cr_status cr_set_allocator(cr_alloc_fn alloc, cr_free_fn free_, void *ctx);
 
 /* Frees the library's cached device and host workspaces. */
 cr_status cr_release(void);

@@ -19,7 +19,11 @@ CR_POLICY_DEPTH_FIRST, CR_POLICY_P_CHUNK, CR_POLICY_VAR_BY_VAR, CR_POLICY_LEARNE
 EXPORTS = ["cr_query_dims", "cr_monomials", "cr_precision", "cr_residue_words", "cr_check_smooth",
            "cr_frobenius_batch", "cr_frobenius", "cr_frobenius_batch_noalloc", "cr_newton_polygon", "cr_policy_cost",
            "cr_mlp_create", "cr_mlp_destroy", "cr_mlp_weights", "cr_mlp_forward", "cr_mlp_grad", "cr_mlp_train",
-           "cr_trace_policy", "cr_autotune", "cr_autotune_cache", "cr_release", "cr_last_error"]
+           "cr_trace_policy", "cr_autotune", "cr_autotune_cache", "cr_set_allocator", "cr_release", "cr_last_error"]
+
+# hook types of cr_set_allocator: alloc(bytes, ctx) -> device pointer, free(ptr, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class cr_family(ctypes.Structure):
@@ -105,6 +109,7 @@ def lib():
         L.cr_trace_policy.argtypes = [P(cr_family), i32, P(u32), i32, P(f32), P(f32), P(i32)]
         L.cr_autotune.argtypes = [P(cr_family), i32, P(i32), P(u32), i32, P(cr_tuning), vp]
         L.cr_autotune_cache.argtypes = [ctypes.c_char_p]
+        L.cr_set_allocator.argtypes = [ALLOC_FN, FREE_FN, ctypes.c_void_p]
         L.cr_release.argtypes = []
         L.cr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -347,6 +352,23 @@ def cr_autotune(fam, primes, coeffs, trials=2, stream=None):
 def cr_autotune_cache(path):
     """Persist autotuner results in `path` (None: stop)."""
     _check(lib().cr_autotune_cache(path.encode() if path is not None else None))
+
+
+_hooks = []  # every ctypes callback pair installed: blocks of live cr_mlp handles return through their own
+
+
+def cr_set_allocator(alloc=None, free=None):
+    """Install device-memory hooks: alloc(nbytes) -> device address (int, 0 on
+    failure) and free(address); both None restores hipMalloc / hipFree."""
+    if (alloc is None) != (free is None):
+        raise ValueError("cr_set_allocator needs both hooks or neither")
+    if alloc is None:
+        _check(lib().cr_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    a = ALLOC_FN(lambda nbytes, _ctx: int(alloc(int(nbytes))) or None)
+    f = FREE_FN(lambda ptr, _ctx: free(int(ptr)))
+    _check(lib().cr_set_allocator(a, f, None))
+    _hooks.append((a, f))
 
 
 def cr_release():

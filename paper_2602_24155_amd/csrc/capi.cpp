@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "device_layout.hpp"
+#include "devmem.hpp"
 #include "host.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
@@ -90,6 +91,7 @@ cr_status fail(cr_status st, const std::string &msg) {
 struct Arena {
     void *dev = nullptr;
     size_t dev_cap = 0;
+    DevBlock block;  // the device buffer of a growing arena
     void *host = nullptr;
     size_t host_cap = 0;
     bool fixed = false;
@@ -109,10 +111,11 @@ struct Arena {
         }
         if (dbytes > dev_cap) {
             const size_t cap = std::max(dbytes, dev_cap + dev_cap / 2);
-            if (dev) (void)hipFree(dev);
+            dev_free(block);
             dev = nullptr;
             dev_cap = 0;
-            if (hipMalloc(&dev, cap) != hipSuccess) return false;
+            if (!dev_alloc(block, cap)) return false;
+            dev = block.ptr;
             dev_cap = cap;
         }
         if (hbytes > host_cap) {
@@ -127,7 +130,7 @@ struct Arena {
     }
     void release() {
         if (fixed) return;
-        if (dev) (void)hipFree(dev);
+        dev_free(block);
         if (host) (void)hipHostFree(host);
         dev = host = nullptr;
         dev_cap = host_cap = 0;
@@ -504,6 +507,14 @@ struct BatchCtx {
             use_bins = pairs = false;
             device_psi = true;
             psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
+        }
+        // without an MFMA kernel the 64-bit VALU kernel reads psi[:, cols(v)] from memory
+        // for every step of every vector; beyond 2^20 entries (cubic threefolds and
+        // fourfolds) that is hours per hypersurface, so such families are refused
+        if (!want_mfma && (size_t)F->nsrc * F->tgt.count > ((size_t)1 << 20)) {
+            err = "no device path for this family: psi has " + std::to_string((size_t)F->nsrc * F->tgt.count) +
+                  " entries (the 64-bit kernel handles up to 2^20)";
+            return false;
         }
         return true;
     }
@@ -1251,6 +1262,16 @@ cr_status cr_release(void) {
     for (Arena &a : g_arenas) a.release();
     g_psi_arena.release();
     return CR_OK;
+}
+
+cr_status cr_set_allocator(cr_alloc_fn alloc, cr_free_fn free_, void *ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr)) return fail(CR_EINVAL, "cr_set_allocator needs both hooks or neither");
+    std::lock_guard<std::mutex> lk(g_mutex);
+    // cached graphs hold the old workspaces' addresses
+    clear_graphs();
+    for (Arena &a : g_arenas) a.release();
+    g_psi_arena.release();
+    return set_allocator(alloc, free_, ctx);
 }
 
 // psi of every item of a call in one k_psi launch on the auxiliary stream

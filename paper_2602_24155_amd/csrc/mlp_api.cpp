@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "devmem.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
 
@@ -28,34 +29,54 @@ struct cr_mlp {
     float *W = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;  // device, CR_MLP_PARAMS (+1 for grad)
     float *X = nullptr, *T = nullptr, *Y = nullptr, *part = nullptr;  // device scratch for rows_cap rows
     float *losses = nullptr;
+    DevBlock bW, bm, bv, bgrad, bX, bT, bY, bpart, blosses;  // the blocks behind the pointers above
     size_t rows_cap = 0, loss_cap = 0;
     int64_t adam_t = 0;
 
+    static bool take(DevBlock &b, float *&ptr, size_t bytes) {
+        dev_free(b);
+        ptr = nullptr;
+        if (!dev_alloc(b, bytes)) return false;
+        ptr = static_cast<float *>(b.ptr);
+        return true;
+    }
+    static void drop(DevBlock &b, float *&ptr) {
+        dev_free(b);
+        ptr = nullptr;
+    }
     bool ensure_rows(size_t rows) {
         if (rows <= rows_cap) return true;
         const size_t cap = std::max(rows, rows_cap + rows_cap / 2);
-        (void)hipFree(X);
-        (void)hipFree(T);
-        (void)hipFree(Y);
-        (void)hipFree(part);
-        X = T = Y = part = nullptr;
+        drop(bX, X);
+        drop(bT, T);
+        drop(bY, Y);
+        drop(bpart, part);
         rows_cap = 0;
         const size_t nb = (cap + 63) / 64;
-        if (hipMalloc(&X, cap * CR_MLP_INPUTS * sizeof(float)) != hipSuccess) return false;
-        if (hipMalloc(&T, cap * sizeof(float)) != hipSuccess) return false;
-        if (hipMalloc(&Y, cap * sizeof(float)) != hipSuccess) return false;
-        if (hipMalloc(&part, nb * (CR_MLP_PARAMS + 1) * sizeof(float)) != hipSuccess) return false;
+        if (!take(bX, X, cap * CR_MLP_INPUTS * sizeof(float))) return false;
+        if (!take(bT, T, cap * sizeof(float))) return false;
+        if (!take(bY, Y, cap * sizeof(float))) return false;
+        if (!take(bpart, part, nb * (CR_MLP_PARAMS + 1) * sizeof(float))) return false;
         rows_cap = cap;
         return true;
     }
     bool ensure_losses(size_t n) {
         if (n <= loss_cap) return true;
-        (void)hipFree(losses);
-        losses = nullptr;
         loss_cap = 0;
-        if (hipMalloc(&losses, n * sizeof(float)) != hipSuccess) return false;
+        if (!take(blosses, losses, n * sizeof(float))) return false;
         loss_cap = n;
         return true;
+    }
+    void release() {
+        drop(bW, W);
+        drop(bm, m);
+        drop(bv, v);
+        drop(bgrad, grad);
+        drop(bX, X);
+        drop(bT, T);
+        drop(bY, Y);
+        drop(bpart, part);
+        drop(blosses, losses);
     }
 };
 
@@ -117,8 +138,8 @@ cr_status cr_mlp_create(const float *weights, uint64_t seed, cr_mlp **out) {
     cr_mlp *m = new cr_mlp();
     (void)hipGetDevice(&m->device);
     const size_t bytes = sizeof(float) * (CR_MLP_PARAMS + 1);
-    bool ok = hipMalloc(&m->W, bytes) == hipSuccess && hipMalloc(&m->m, bytes) == hipSuccess &&
-              hipMalloc(&m->v, bytes) == hipSuccess && hipMalloc(&m->grad, bytes) == hipSuccess;
+    bool ok = cr_mlp::take(m->bW, m->W, bytes) && cr_mlp::take(m->bm, m->m, bytes) &&
+              cr_mlp::take(m->bv, m->v, bytes) && cr_mlp::take(m->bgrad, m->grad, bytes);
     std::vector<float> zero(CR_MLP_PARAMS + 1, 0.f);
     ok = ok && hipMemcpy(m->W, w.data(), sizeof(float) * CR_MLP_PARAMS, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->m, zero.data(), bytes, hipMemcpyHostToDevice) == hipSuccess &&
@@ -134,15 +155,7 @@ cr_status cr_mlp_create(const float *weights, uint64_t seed, cr_mlp **out) {
 
 cr_status cr_mlp_destroy(cr_mlp *m) {
     if (!m) return CR_OK;
-    (void)hipFree(m->W);
-    (void)hipFree(m->m);
-    (void)hipFree(m->v);
-    (void)hipFree(m->grad);
-    (void)hipFree(m->X);
-    (void)hipFree(m->T);
-    (void)hipFree(m->Y);
-    (void)hipFree(m->part);
-    (void)hipFree(m->losses);
+    m->release();
     delete m;
     return CR_OK;
 }

@@ -151,3 +151,18 @@ def test_single_hypersurface_entry_rejects_bad_input_without_device():
     with pytest.raises(C.CrError) as e:
         C.cr_frobenius(C.family(3, 5), 9, [1] * 21)
     assert e.value.status in (C.CR_ENOTPRIME, C.CR_EINVAL)
+
+
+def test_allocator_hook_arguments_without_device():
+    """cr_set_allocator: one hook without the other is CR_EINVAL; installing and
+    removing hooks before any device work allocates nothing."""
+    L = C.lib()
+    calls = []
+    alloc = C.ALLOC_FN(lambda n, ctx: calls.append(n) or None)
+    assert L.cr_set_allocator(alloc, C.FREE_FN(), None) == C.CR_EINVAL
+    assert L.cr_set_allocator(C.ALLOC_FN(), C.FREE_FN(lambda p, ctx: None), None) == C.CR_EINVAL
+    with pytest.raises(ValueError):
+        C.cr_set_allocator(alloc=lambda n: 0)
+    C.cr_set_allocator(lambda n: calls.append(n) or 0, lambda ptr: None)
+    C.cr_set_allocator()
+    assert calls == []
