@@ -95,9 +95,10 @@ typedef struct {
     int32_t n_series; /* series order override N_m for every m; 0 = r + 1 */
     int32_t engine;   /* reduction kernel: 0 = auto (int8-digit MFMA kernel with the gather on
                          the accumulators and two interleaved tiles per workgroup -- the
-                         products of one tile overlap the finishing of the other -- when the
-                         family and digit count allow it, else the same kernel with one tile per
-                         workgroup, for four-variable families with S = all (quartic K3
+                         products of one tile overlap the finishing of the other -- for the
+                         items whose digit count allows it (5 or 8 digits for plane quintics),
+                         the same kernel with one tile per workgroup for the other items of the
+                         batch (10 digits), for four-variable families with S = all (quartic K3
                          surfaces) the quad kernel, else the 64-bit VALU kernel), 1 = 64-bit VALU
                          kernel, 2 = int8-digit MFMA kernel with the gather through LDS, 3 =
                          register-gather MFMA kernel with one tile per workgroup, 4 = quad
@@ -138,7 +139,7 @@ typedef struct {
     double assemble_ms;      /* device time of the Griffiths-Dwork assembly kernel */
     double finish_ms;        /* host unscaling and L-polynomial recovery */
     int32_t engine;          /* kernel that ran: 0 / 3 / 2 = int8-digit MFMA (register gather with tile
-                                pairs / with one tile / LDS gather), 4 = int8-digit MFMA quad kernel
+                                pairs for some or all items / with one tile / LDS gather), 4 = int8-digit MFMA quad kernel
                                 (four variables), 1 = 64-bit VALU */
     int32_t policy;          /* policy whose plan ran */
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */

@@ -534,6 +534,7 @@ struct SubBatch {
     int ct = 32, nphase = 0, fallbacks = 0;
     struct Launch {
         int phase, key, tile0, ntiles;
+        bool pairs;  // tile pairs (k_reduce_mfma5), else single tiles
     };
     std::vector<Launch> launches;
     std::vector<size_t> comb_first, comb_count;
@@ -622,9 +623,10 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
     if (sb.use_mfma && !sb.use_bins && !ctx.quad && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
-    sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;  // folded psi digits
-    for (int li = 0; li < nlive && sb.use_pairs; li++)
-        if (!mfma5_supports(df, sb.dps[sb.live[li]].D)) sb.use_pairs = false;
+    // tile pairs are chosen per digit count: the items whose digit count the
+    // pair kernel takes get their psi digits folded, the others run on single tiles
+    sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;
+    auto pairs_for = [&](int D) { return sb.use_pairs && mfma5_supports(df, D); };
     if (sb.use_mfma && !sb.use_bins && !ctx.quad && ctx.device_psi)
         sb.use_mfma = false;  // device packing follows the bin layout (or the quad placement)
     if (!sb.use_mfma && ctx.device_psi && ctx.want_mfma) {
@@ -677,7 +679,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                 }
                 nvec += ph.size();
             }
-            if (sb.use_pairs && (int)tiles.size() > first) {
+            if (pairs_for(key % 100) && (int)tiles.size() > first) {
                 // pairs of tiles of one item (an odd one out gets an empty partner),
                 // longest pairs first
                 std::vector<std::pair<DevTile, DevTile>> pr;
@@ -702,13 +704,13 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                     tiles.push_back(q.first);
                     tiles.push_back(q.second);
                 }
-                sb.launches.push_back({t, key, first, (int)pr.size()});
+                sb.launches.push_back({t, key, first, (int)pr.size(), true});
                 continue;
             }
             // longest tiles first, so that the last wave of workgroups is short
             std::stable_sort(tiles.begin() + first, tiles.end(),
                              [](const DevTile &x, const DevTile &y) { return x.steps > y.steps; });
-            if ((int)tiles.size() > first) sb.launches.push_back({t, key, first, (int)tiles.size() - first});
+            if ((int)tiles.size() > first) sb.launches.push_back({t, key, first, (int)tiles.size() - first, false});
         }
     std::vector<int32_t> row0(nlive, 0);
     std::vector<size_t> coef0(nlive, 0), fin0(nlive, 0), apack_off(nlive, 0);
@@ -895,6 +897,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             dd.h = dp.h;
             dd.ds = dp.ds;
             dd.z32 = dp.z32;
+            dd.fold = sb.use_pairs && mfma5_supports(df, dp.D) ? 1 : 0;
             dd.chain0 = 0;
             dd.nchain = it.nchain();
             dd.apack = reinterpret_cast<const int8_t *>(db + apack_off[li]);
@@ -991,7 +994,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                         e = launch_reduce_quad(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_qslots),
                                                errp, pgrid, queue + li, rs);
-                    else if (sb.use_pairs)
+                    else if (L.pairs)
                         e = launch_reduce_mfma5(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
                                                 errp, Dg, z32g, pgrid, queue + li, rs);
@@ -1013,7 +1016,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         std::string sig = std::to_string((uintptr_t)db) + ":" + std::to_string(sb.nphase) + ":" + std::to_string(pgrid);
         for (auto &L : sb.launches)
             sig += "|" + std::to_string(L.phase) + "," + std::to_string(L.key) + "," + std::to_string(L.tile0) + "," +
-                   std::to_string(L.ntiles);
+                   std::to_string(L.ntiles) + (L.pairs ? "p" : "s");
         for (int t = 0; t < sb.nphase; t++) sig += "/" + std::to_string(sb.comb_first[t]) + "," + std::to_string(sb.comb_count[t]);
         for (size_t o : {sb.o_items, sb.o_tiles, sb.o_ditems, sb.o_tables, sb.o_cu, sb.o_cg, sb.o_cp, sb.o_vx,
                          sb.o_comb, sb.o_msrc, sb.o_malpha, sb.o_err, sb.o_hbuf, sb.o_store, sb.o_queue})
@@ -1514,7 +1517,9 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
             stats->reduce_launches += (int64_t)sb.launches.size();
             stats->fallbacks += sb.fallbacks;
             if (!sb.live.empty()) {
-                const int e = sb.use_mfma ? (ctx.quad ? 4 : (sb.use_pairs ? 0 : (sb.use_bins ? 3 : 2))) : 1;
+                bool any_pairs = false;
+                for (auto &L : sb.launches) any_pairs = any_pairs || L.pairs;
+                const int e = sb.use_mfma ? (ctx.quad ? 4 : (any_pairs ? 0 : (sb.use_bins ? 3 : 2))) : 1;
                 // a sub-batch that fell back to the VALU kernel makes the call report it
                 if (stats->engine < 0 || e == 1) stats->engine = e;
             }

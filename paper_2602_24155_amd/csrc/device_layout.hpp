@@ -91,6 +91,7 @@ struct DevDigitItem {
     int32_t h;            // Horner split position
     int32_t ds;           // digit split position
     int32_t z32;          // 1: the weighted digit sums and the carry sums fit int32
+    int32_t fold;         // 1: psi digits packed for the tile-pair kernel (folded last K-block)
     int32_t chain0, nchain;
     const int8_t *apack;  // NRT x D x NKB x 64 lanes x 16 bytes: psi digits in MFMA A-fragment order
     int8_t *apack_out;    // the same buffer, written by k_pack_psi

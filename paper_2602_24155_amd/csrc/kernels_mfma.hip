@@ -1421,7 +1421,9 @@ bool mfma5_supports(const DevFamily &fam, int D) {
     if (fam.s > 32 * (nkb - 1)) return false;  // parked digits stay below the folded block
     // the digits of an ending chain are parked at columns r < s of its rows
     if (fam.s > nkb * 32) return false;
-    return (nrt == 4 && (D == 5 || D == 8 || D == 10)) || (nrt == 2 && (D == 3 || D == 6));
+    // the two tiles' accumulators (2 D x 16 registers) must fit the 256 AGPRs:
+    // D = 10 (plane quintics at p = 17 .. 29) would spill them to scratch
+    return (nrt == 4 && (D == 5 || D == 8)) || (nrt == 2 && (D == 3 || D == 6));
 }
 
 hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int npairs,
@@ -1444,7 +1446,6 @@ hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, 
     CRF_LAUNCH5(2, 2, 6)
     CRF_LAUNCH5(4, 3, 5)
     CRF_LAUNCH5(4, 3, 8)
-    CRF_LAUNCH5(4, 3, 10)
 #undef CRF_LAUNCH5
     return hipErrorInvalidValue;
 }

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kPsiThreads) void k_psi_global(const DevItem *__res
 // source rows placed by the bin layout:
 // apack[(((rt*D + i)*nkb + kb)*64 + lane)*16 + jj] = digit i of
 // psi[slot_src(2 rt + (lane%32 >> 2 & 1), (lane%32 >> 3) * 4 + lane%4)][32 kb + (lane/32)*16 + jj].
-// With fold set (tile-pair kernel), the last K-block holds A'_i instead: its
+// With fold set and the item's fold flag (tile-pair kernel), the last K-block holds A'_i instead: its
 // k-slot R2 J + t (R2 = T - 32 (nkb - 1) rows) carries digit i - J of
 // psi[row][32 (nkb - 1) + t] for J <= i, 0 otherwise; the reduction kernel
 // stores digit J of those target rows at the same k-slot of plane 0.
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ it
     const int rho = lane & 31, hh = (rho >> 2) & 1, js = (rho >> 3) * 4 + (rho & 3);
     const int row = slot_src[(2 * rt + hh) * 16 + js];
     const int kslot = (lane >> 5) * 16 + jj;
-    const bool folded = fold && kb == nkb - 1;
+    const bool folded = fold && dd.fold && kb == nkb - 1;
     const int base = 32 * (nkb - 1), r2 = T - base;
     const int Jf = folded ? kslot / r2 : 0;  // plane whose folded rows this k-slot carries
     const int k = folded ? base + kslot % r2 : 32 * kb + kslot;
