@@ -354,6 +354,7 @@ def cr_autotune_cache(path):
     _check(lib().cr_autotune_cache(path.encode() if path is not None else None))
 
 
+_hook_errors = []  # exceptions raised inside the Python hooks (they cannot cross the C ABI)
 _hooks = []  # every ctypes callback pair installed: blocks of live cr_mlp handles return through their own
 
 
@@ -365,8 +366,20 @@ def cr_set_allocator(alloc=None, free=None):
     if alloc is None:
         _check(lib().cr_set_allocator(ALLOC_FN(), FREE_FN(), None))
         return
-    a = ALLOC_FN(lambda nbytes, _ctx: int(alloc(int(nbytes))) or None)
-    f = FREE_FN(lambda ptr, _ctx: free(int(ptr)))
+    def call_alloc(nbytes, _ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception as e:  # the library sees NULL (CR_ENOMEM)
+            _hook_errors.append(e)
+            return None
+
+    def call_free(ptr, _ctx):
+        try:
+            free(int(ptr))
+        except Exception as e:
+            _hook_errors.append(e)
+
+    a, f = ALLOC_FN(call_alloc), FREE_FN(call_free)
     _check(lib().cr_set_allocator(a, f, None))
     _hooks.append((a, f))
 
