@@ -9,6 +9,7 @@
 #include <functional>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -286,6 +287,56 @@ class Pool {
     bool stop_ = false;
 };
 thread_local bool Pool::in_task = false;
+
+// Frees what a finished call leaves behind (the host state of its items and
+// plans: thousands of heap blocks for a batch of hundreds of hypersurfaces)
+// on a thread of its own, so that the call returns without waiting for the
+// frees (about half a millisecond per call for 256 plane quintics).
+class Reaper {
+  public:
+    static Reaper &get() {
+        static Reaper r;
+        return r;
+    }
+    void post(std::function<void()> job) {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            q_.push_back(std::move(job));
+        }
+        cv_.notify_one();
+    }
+    ~Reaper() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_one();
+        th_.join();
+    }
+
+  private:
+    Reaper() : th_([this] { loop(); }) {}
+    void loop() {
+        std::unique_lock<std::mutex> lk(m_);
+        for (;;) {
+            cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+            while (!q_.empty()) {
+                std::function<void()> job = std::move(q_.front());
+                q_.pop_front();
+                lk.unlock();
+                job();
+                job = nullptr;
+                lk.lock();
+            }
+            if (stop_) return;
+        }
+    }
+    std::mutex m_;
+    std::condition_variable cv_;
+    std::deque<std::function<void()>> q_;
+    bool stop_ = false;
+    std::thread th_;  // last: starts after the members it uses exist
+};
 
 template <class Fn>
 void parallel_for(int count, Fn fn) {
@@ -1411,15 +1462,24 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
     }
     // Sub-batches: the host prepares sub-batch k + 1 while the device reduces
     // sub-batch k.  Sizes follow the width P of the host pool (each item's
-    // setup is one task): the first sub-batch, whose host setup and psi the
-    // device waits for, is one round of the pool (P items), the others two.
+    // setup is one task).  Where an item's host setup is long against its
+    // device work (surfaces: tens of milliseconds per item), the first
+    // sub-batch, whose setup the device waits for, is one round of the pool
+    // (P items) and the others two.  For plane curves (setup well under a
+    // millisecond per item) the device time lost in launch tails outweighs
+    // that wait: the first sub-batch is two rounds and the others four
+    // (256 plane quintics: 5 launches instead of 9, 14.3 against 14.8 ms).
+    // The allocation-free entry point keeps the smaller sizes (its
+    // sub-batches share one fixed workspace).
     const int P = Pool::get().width();
+    const bool small = ctx.F->g.count <= 64 && !noalloc;
+    const int sub0 = small ? 2 * P : P, later = small ? 4 * P : 2 * P;
     std::vector<int> cut{0};
-    if (count <= 2 * P) {
+    if (count <= sub0 + P) {
         cut.push_back(count);
     } else {
-        cut.push_back(P);
-        while (cut.back() < count) cut.push_back(std::min(count, cut.back() + 2 * P));
+        cut.push_back(sub0);
+        while (cut.back() < count) cut.push_back(std::min(count, cut.back() + later));
     }
     const int S = (int)cut.size() - 1;
     std::vector<SubBatch> sub(S);
@@ -1528,6 +1588,8 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
         stats->psi_ms += psi_all_ms;
         stats->device_ms += psi_all_ms;
     }
+    auto spent = std::make_shared<std::vector<SubBatch>>(std::move(sub));
+    Reaper::get().post([spent]() mutable { spent.reset(); });
     return first;
 }
 
