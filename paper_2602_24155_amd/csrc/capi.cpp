@@ -1462,20 +1462,23 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
     }
     // Sub-batches: the host prepares sub-batch k + 1 while the device reduces
     // sub-batch k.  Sizes follow the width P of the host pool (each item's
-    // setup is one task).  Where an item's host setup is long against its
-    // device work (surfaces: tens of milliseconds per item), the first
-    // sub-batch, whose setup the device waits for, is one round of the pool
-    // (P items) and the others two.  For plane curves (setup well under a
-    // millisecond per item) the device time lost in launch tails outweighs
-    // that wait: the first sub-batch is two rounds and the others four
-    // (256 plane quintics: 5 launches instead of 9, 14.3 against 14.8 ms).
-    // The allocation-free entry point keeps the smaller sizes (its
-    // sub-batches share one fixed workspace).
+    // setup is one task).  Where an item's host setup is about as long as its
+    // share of the device work (quartic K3 surfaces: one pool round of setup,
+    // 64 ms, against 82 ms of reduction for P = 16 surfaces), every
+    // sub-batch is one round, so that the setup of the next one always hides
+    // behind the reduction of the current one (64 K3 surfaces: 401 against
+    // 446-458 ms per call with a second sub-batch of two rounds).  For plane
+    // curves (setup well under a millisecond per item) the device time lost
+    // in launch tails outweighs the wait for a larger first sub-batch: it is
+    // two rounds and the others four (256 plane quintics: 5 launches instead
+    // of 9, 14.3 against 14.8 ms).  The allocation-free entry point keeps one
+    // round, then two (its sub-batches share one fixed workspace).
     const int P = Pool::get().width();
-    const bool small = ctx.F->g.count <= 64 && !noalloc;
-    const int sub0 = small ? 2 * P : P, later = small ? 4 * P : 2 * P;
+    const bool small = ctx.F->g.count <= 64;
+    const int sub0 = small && !noalloc ? 2 * P : P;
+    const int later = noalloc ? 2 * P : (small ? 4 * P : P);
     std::vector<int> cut{0};
-    if (count <= sub0 + P) {
+    if (count <= sub0 + (small || noalloc ? P : 0)) {
         cut.push_back(count);
     } else {
         cut.push_back(sub0);

@@ -372,6 +372,15 @@ static std::vector<int> nonpivot_columns_mod_p(std::vector<int> a, int rows, int
 // order; each row's pivot is its first column holding a unit after the
 // earlier pivots were cleared.  Returns false if some row has no unit left
 // (A is not surjective mod p).
+//
+// Left-looking form of that elimination: row r is brought up to date with
+// the earlier pivot rows (in the state they had when they became pivots) in
+// one pass, with the products summed in 128 bits and reduced once per 128
+// terms (sparse pivot rows by their nonzero columns); the pivot rows are
+// then cleared of the later pivot columns (back substitution, right half
+// only).  The pivots, and so X, are those of
+// plain Gauss-Jordan elimination in row order: the reduced rows are
+// determined by the pivot columns.
 static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int C, std::vector<u64> &X) {
     const int W = C + R;
     const u64 q = mq.q;
@@ -380,25 +389,43 @@ static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int 
         std::memcpy(&a[(size_t)r * W], &A[(size_t)r * C], sizeof(u64) * C);
         a[(size_t)r * W + C + r] = 1;
     }
-    std::vector<int> piv(R, -1), nz;
+    std::vector<int> piv(R, -1);
     std::vector<char> used(C, 0);
-    nz.reserve(W);
-    // Shoup's quotient floor(y 2^64 / q) of a multiplier y < q from the 128-bit
-    // reciprocal floor((2^128 - 1) / q): the estimate (y * rq) >> 64 is at most 2
-    // below the true value, fixed by comparing y 2^64 - est q with q
-    u128 rq = ~(u128)0 / q;
-    auto shoup = [&](u64 y) {
-        const u128 yh = (u128)y * (u64)(rq >> 64), yl = (u128)y * (u64)rq;
-        u64 est = (u64)((yh + (yl >> 64)));
-        u128 rem = ((u128)y << 64) - (u128)est * q;
-        while (rem >= q) {
-            rem -= q;
-            est++;
-        }
-        return est;
+    std::vector<u128> acc(W);
+    // nonzero columns of each pivot row when it is sparse (empty: dense)
+    std::vector<std::vector<int>> nzc(R);
+    auto index_row = [&](const u64 *P, int k0, std::vector<int> &out) {
+        out.clear();
+        int cnt = 0;
+        for (int k = k0; k < W; k++) cnt += P[k] != 0;
+        if (2 * cnt >= W - k0) return;
+        for (int k = k0; k < W; k++)
+            if (P[k]) out.push_back(k);
     };
     for (int r = 0; r < R; r++) {
         u64 *row = &a[(size_t)r * W];
+        // apply the pivot rows in order, products summed in 128 bits: the
+        // multiplier of pivot row j is the entry at c_j after pivots 0 .. j-1
+        if (r > 0) {
+            for (int k = 0; k < W; k++) acc[k] = row[k];
+            for (int j = 0, n = 0; j < r; j++) {
+                const int cj = piv[j];
+                const u64 f = mq.reduce(acc[cj]);
+                acc[cj] = f;
+                if (!f) continue;
+                const u64 m = q - f;
+                const u64 *P = &a[(size_t)j * W];
+                if (nzc[j].empty())
+                    for (int k = 0; k < W; k++) acc[k] += (u128)m * P[k];
+                else
+                    for (int k : nzc[j]) acc[k] += (u128)m * P[k];
+                if (++n == 128) {
+                    for (int k = 0; k < W; k++) acc[k] = mq.reduce(acc[k]);
+                    n = 0;
+                }
+            }
+            for (int k = 0; k < W; k++) row[k] = mq.reduce(acc[k]);
+        }
         int c = -1;
         for (int k = 0; k < C; k++)
             if (!used[k] && row[k] % (u64)p) {
@@ -406,32 +433,39 @@ static bool right_inverse(const ModQ &mq, int p, std::vector<u64> A, int R, int 
                 break;
             }
         if (c < 0) return false;
-        u64 inv = mq.inv(row[c]);
-        nz.clear();
+        const u64 inv = mq.inv(row[c]);
         for (int k = 0; k < W; k++)
-            if (row[k]) {
-                row[k] = mq.mul(row[k], inv);
-                nz.push_back(k);
-            }
-        for (int r2 = 0; r2 < R; r2++) {
-            if (r2 == r) continue;
-            u64 *o = &a[(size_t)r2 * W];
-            const u64 f = o[c];
-            if (!f) continue;
-            // o -= f * row (mod q) with Shoup's precomputed quotient of f
-            const u64 nf = q - f;
-            const u64 fs = shoup(nf);
-            for (int k : nz) {
-                const u64 x = row[k];
-                const u64 qh = (u64)(((u128)fs * x) >> 64);
-                u64 t = nf * x - qh * q;  // nf x mod q, in [0, 2q)
-                if (t >= q) t -= q;
-                t += o[k];
-                o[k] = t >= q ? t - q : t;
-            }
-        }
+            if (row[k]) row[k] = mq.mul(row[k], inv);
         used[c] = 1;
         piv[r] = c;
+        index_row(row, 0, nzc[r]);
+    }
+    // back substitution on the right half: row r loses the later pivot
+    // columns, row R - 1 first
+    index_row(&a[(size_t)(R - 1) * W], C, nzc[R - 1]);
+    for (int r = R - 2; r >= 0; r--) {
+        u64 *row = &a[(size_t)r * W];
+        bool any = false;
+        for (int j = r + 1; j < R && !any; j++) any = row[piv[j]] != 0;
+        if (any) {
+            for (int k = C; k < W; k++) acc[k] = row[k];
+            for (int j = r + 1, n = 0; j < R; j++) {
+                const u64 f = row[piv[j]];
+                if (!f) continue;
+                const u64 m = q - f;
+                const u64 *P = &a[(size_t)j * W];
+                if (nzc[j].empty())
+                    for (int k = C; k < W; k++) acc[k] += (u128)m * P[k];
+                else
+                    for (int k : nzc[j]) acc[k] += (u128)m * P[k];
+                if (++n == 128) {
+                    for (int k = C; k < W; k++) acc[k] = mq.reduce(acc[k]);
+                    n = 0;
+                }
+            }
+            for (int k = C; k < W; k++) row[k] = mq.reduce(acc[k]);
+        }
+        index_row(row, C, nzc[r]);
     }
     X.assign((size_t)C * R, 0);
     for (int r = 0; r < R; r++) std::memcpy(&X[(size_t)piv[r] * R], &a[(size_t)r * W + C], sizeof(u64) * R);

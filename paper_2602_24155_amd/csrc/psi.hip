@@ -203,9 +203,21 @@ __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ it
     if (x >= Q) x -= Q;
     int8_t *out = dd.apack_out + ((size_t)(rt * D) * nkb + kb) * 1024 + (size_t)lane * 16 + jj;
     int8_t dig[16];
+    // x < Q' < 2^52 is exact in fp64: the quotient by B from the product with
+    // 1 / B is off by at most one, which the remainder's range corrects (a
+    // 64-bit integer division costs far more on the GPU)
+    const double invB = 1.0 / (double)dd.B;
     for (int i = 0; i < D; i++) {
-        const uint64_t qd = x / B;
-        dig[i] = (int8_t)((int)(x - qd * B) - dd.halfB);
+        uint64_t qd = (uint64_t)((double)x * invB);
+        int64_t r = (int64_t)(x - qd * B);
+        if (r < 0) {
+            qd--;
+            r += (int64_t)B;
+        } else if (r >= (int64_t)B) {
+            qd++;
+            r -= (int64_t)B;
+        }
+        dig[i] = (int8_t)((int)r - dd.halfB);
         x = qd;
     }
     // unfolded: fragment i holds digit i; folded: fragment i holds digit i - Jf
