@@ -1469,20 +1469,22 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
     // behind the reduction of the current one (64 K3 surfaces: 401 against
     // 446-458 ms per call with a second sub-batch of two rounds).  For plane
     // curves (setup well under a millisecond per item) the device time lost
-    // in launch tails outweighs the wait for a larger first sub-batch: it is
-    // two rounds and the others four (256 plane quintics: 5 launches instead
-    // of 9, 14.3 against 14.8 ms).  The allocation-free entry point keeps one
-    // round, then two (its sub-batches share one fixed workspace).
+    // in launch tails outweighs the wait for a larger first sub-batch: the
+    // sub-batches grow by two rounds each, 2P, 4P, 6P, ... (256 plane
+    // quintics: 32, 64, 96 and 64 curves, 4 launches instead of 9, 13.7
+    // against 14.8 ms; the mixed-prime batch 24.3 against 26.0 ms with 2P
+    // then 4P).  The allocation-free entry point keeps one round, then two
+    // (its sub-batches share one fixed workspace).
     const int P = Pool::get().width();
     const bool small = ctx.F->g.count <= 64;
-    const int sub0 = small && !noalloc ? 2 * P : P;
-    const int later = noalloc ? 2 * P : (small ? 4 * P : P);
     std::vector<int> cut{0};
-    if (count <= sub0 + (small || noalloc ? P : 0)) {
+    if (count <= (noalloc ? 2 * P : (small ? 3 * P : P))) {
         cut.push_back(count);
     } else {
-        cut.push_back(sub0);
-        while (cut.back() < count) cut.push_back(std::min(count, cut.back() + later));
+        for (int k = 0; cut.back() < count; k++) {
+            const int size = noalloc ? (k == 0 ? P : 2 * P) : (small ? 2 * P * (k + 1) : P);
+            cut.push_back(std::min(count, cut.back() + size));
+        }
     }
     const int S = (int)cut.size() - 1;
     std::vector<SubBatch> sub(S);
