@@ -105,14 +105,25 @@ __device__ __forceinline__ void load_frags(const int8_t *base, int rt, int kb, v
 }
 
 // Balanced base-B digits of x in [0, q) (q | Q'), written D planes apart.
+// v < Q' < 2^52 is exact in fp64: the quotient by B from the product with
+// 1 / B is off by at most one, which the remainder's range corrects (a 64-bit
+// integer division costs far more).
 template <int D, int XS>
-__device__ __forceinline__ void put_digits_q(int8_t *xp, uint64_t x, uint64_t Qp, int B, int halfB) {
+__device__ __forceinline__ void put_digits_q(int8_t *xp, uint64_t x, uint64_t Qp, int B, double invB, int halfB) {
     uint64_t v = x + (Qp - 1) / 2;  // unsigned digits of x + sum_k halfB B^k, mod Q'
     if (v >= Qp) v -= Qp;
 #pragma unroll
     for (int k = 0; k < D; k++) {
-        const uint64_t qd = v / (uint64_t)B;
-        xp[k * kQV * XS] = (int8_t)((int)(v - qd * (uint64_t)B) - halfB);
+        uint64_t qd = (uint64_t)((double)v * invB);
+        int64_t r = (int64_t)(v - qd * (uint64_t)B);
+        if (r < 0) {
+            qd--;
+            r += B;
+        } else if (r >= B) {
+            qd++;
+            r -= B;
+        }
+        xp[k * kQV * XS] = (int8_t)((int)r - halfB);
         v = qd;
     }
 }
@@ -151,8 +162,11 @@ __device__ __forceinline__ void emit_q(const double (&z)[D], int r, bool more, c
     int64_t x = 0;
 #pragma unroll
     for (int k = D - 1; k >= 0; k--) x = x * Bi + dg[k];
-    x %= q;
+    // x mod q for |x| < Q' / 2 < 2^51 (exact in fp64): the floored quotient
+    // from the product with 1 / q is off by at most one
+    x -= (int64_t)floor((double)x * (1.0 / (double)q)) * q;
     if (x < 0) x += q;
+    else if (x >= q) x -= q;
     if (x == 0) return;  // outputs were cleared at the start of the tile
     if (vout >= 0) {
         store[(size_t)vout * s + r] = (uint64_t)x;
@@ -234,7 +248,7 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
                     bad |= 2;
                     continue;
                 }
-                put_digits_q<D, XS>(Xbuf + c * XS + col, x, it.Qp, it.B, it.halfB);
+                put_digits_q<D, XS>(Xbuf + c * XS + col, x, it.Qp, it.B, invB, it.halfB);
             }
         }
     }
