@@ -560,8 +560,10 @@ struct BatchCtx {
             psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
         }
         // without an MFMA kernel the 64-bit VALU kernel reads psi[:, cols(v)] from memory
-        // for every step of every vector; beyond 2^20 entries (cubic threefolds and
-        // fourfolds) that is hours per hypersurface, so such families are refused
+        // for every step of every vector, two vectors per workgroup when psi is large;
+        // beyond 2^20 entries (cubic threefolds: 1815 x 1001, 716k column steps over F_7,
+        // some petabytes of psi reads, minutes per hypersurface; cubic fourfolds: 80 million
+        // entries) such families are refused
         if (!want_mfma && (size_t)F->nsrc * F->tgt.count > ((size_t)1 << 20)) {
             err = "no device path for this family: psi has " + std::to_string((size_t)F->nsrc * F->tgt.count) +
                   " entries (the 64-bit kernel handles up to 2^20)";
