@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA, TOP/s
 KERNEL_NAMES = {0: "k_reduce_mfma5", 1: "k_reduce_chains", 2: "k_reduce_mfma", 3: "k_reduce_mfma4",
-                4: "k_reduce_quad"}  # engine that ran
+                4: "k_reduce_quad", 5: "k_reduce_wide"}  # engine that ran
 
 
 def measured_traffic(kernel, workload):

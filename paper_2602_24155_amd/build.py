@@ -9,7 +9,7 @@ OUT = os.path.join(HERE, "libcrfrob.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["host.cpp", "plan.cpp", "capi.cpp", "mlp_api.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip", "psi.hip",
-           "kernels_quad.hip", "workspace.hip", "newton.cpp", "devmem.cpp"]
+           "kernels_quad.hip", "kernels_wide.hip", "workspace.hip", "newton.cpp", "devmem.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -128,7 +128,7 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS, ENGINE_MFMA_SINGLE, ENGINE_QUAD = 0, 1, 2, 3, 4
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA_LDS, ENGINE_MFMA_SINGLE, ENGINE_QUAD, ENGINE_WIDE = 0, 1, 2, 3, 4, 5
 
 
 LAUNCH_GRID, LAUNCH_PERSISTENT, LAUNCH_GRAPH = 0, 1, 2

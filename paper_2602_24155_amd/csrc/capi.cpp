@@ -62,6 +62,14 @@ hipError_t launch_reduce_quad(const DevFamily &fam, const DevDigitItem *items, c
                               const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
                               uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int pgrid, int *queue,
                               hipStream_t stream);
+bool wide_shape(const DevFamily &fam, int &nrt, int &nrtq, int &nkb);
+bool wide_supports_digits(int D);
+size_t wide_scratch_bytes(int D, int grid);
+int wide_grid(int ntiles, int pgrid);
+hipError_t launch_reduce_wide(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
+                              const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
+                              uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int *err, int D, int grid,
+                              int8_t *xscratch, int *queue, hipStream_t stream);
 }  // namespace crf
 
 using namespace crf;
@@ -144,7 +152,7 @@ struct FamilyEntry {
     size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src, off_qslots, off_qslot_src;
     BinLayout bl;  // source-row placement for the register-gather MFMA kernel
     bool bl_ok = false;
-    BinLayout ql;  // row placement of the four-variable quad kernel
+    BinLayout ql;  // row placement of the quad kernel (or of the threefold kernel)
     bool ql_ok = false;
 };
 
@@ -202,7 +210,9 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         if (ss.empty()) ss.assign(16, -1);
         e->off_slot_src = put(ss.data(), ss.size() * 2);
         int qrt = 0, qrtf = 0, qkb = 0;
-        e->ql_ok = quad_shape(shape, qrt, qrtf, qkb) && quad_layout(F, qrt, qrtf, e->ql);
+        // the quad placement (quartic K3 surfaces) or the quint placement (cubic threefolds)
+        e->ql_ok = quad_shape(shape, qrt, qrtf, qkb) ? quad_layout(F, qrt, qrtf, e->ql)
+                                                      : wide_shape(shape, qrt, qrtf, qkb) && wide_layout(F, qrt, qrtf, e->ql);
         if (!e->ql_ok) e->ql.slot.assign(16, 0);
         e->off_qslots = put(e->ql.slot.data(), e->ql.slot.size() * 4);
         std::vector<int16_t> qs(e->ql.slot_src.begin(), e->ql.slot_src.end());
@@ -368,7 +378,7 @@ bool check_family(const cr_family *fam, std::string &err) {
         err = "unsupported nvars/degree";
         return false;
     }
-    if (fam->engine < 0 || fam->engine > 4) {
+    if (fam->engine < 0 || fam->engine > 5) {
         err = "unknown engine";
         return false;
     }
@@ -489,6 +499,7 @@ struct BatchCtx {
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
     bool quad = false;        // four-variable int8-digit MFMA kernel (k_reduce_quad)
+    bool wide = false;        // cubic-threefold int8-digit MFMA kernel (k_reduce_wide)
     bool psi_global = false;  // device psi with [J | I] in global memory (k_psi_global)
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
@@ -550,7 +561,8 @@ struct BatchCtx {
         pairs = f->engine == 0;  // engine 3: the single-tile kernel
         int qrtf = 0;
         quad = (f->engine == 0 || f->engine == 4) && fe->ql_ok && quad_shape(df, nrt, qrtf, nkb);
-        want_mfma = quad || (f->engine == 0 || f->engine == 2 || f->engine == 3) &&
+        wide = !quad && (f->engine == 0 || f->engine == 5) && fe->ql_ok && wide_shape(df, nrt, qrtf, nkb);
+        want_mfma = quad || wide || (f->engine == 0 || f->engine == 2 || f->engine == 3) &&
                     (use_bins ? mfma4_shape(df, nrt, nkb) : mfma_shape(df, nrt, nkb));
         // the LDS-gather kernel (engine 2) keeps host psi and host packing
         device_psi = f->engine != 2 && psi_lds_bytes(F->tgt.count, F->nsrc) <= 150 * 1024;
@@ -558,6 +570,10 @@ struct BatchCtx {
             use_bins = pairs = false;
             device_psi = true;
             psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
+        }
+        if (wide) {  // host psi (its [J | I] is 22 MB), digits packed on the host in the quint placement
+            use_bins = pairs = false;
+            device_psi = false;
         }
         // without an MFMA kernel the 64-bit VALU kernel reads psi[:, cols(v)] from memory
         // for every step of every vector, two vectors per workgroup when psi is large;
@@ -594,6 +610,7 @@ struct SubBatch {
     size_t h_end = 0, o_items = 0, o_tiles = 0, o_ditems = 0, o_tables = 0, o_cu = 0, o_cg = 0, o_cp = 0, o_vx = 0;
     size_t o_comb = 0, o_msrc = 0, o_malpha = 0, o_err = 0, o_Y = 0, o_hbuf = 0, o_store = 0, o_queue = 0;
     size_t o_psi_dev = 0;
+    size_t o_xw = 0;  // threefold kernel: digit planes in global memory
     DevFamily df{};
     hipEvent_t ep = nullptr, epe = nullptr, e0 = nullptr, em = nullptr, e1 = nullptr, edone = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
@@ -644,9 +661,9 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
             int umax = 0;
             for (size_t k = 0; k < it.chain_u.size(); k++) umax = std::max<int>(umax, it.chain_u[k]);
             const u64 wtmax = (u64)umax + (u64)F.g.deg + 1;
-            if (ctx.quad) {
+            if (ctx.quad || ctx.wide) {
                 if (quad_digit_params(it.p, it.M, F.tgt.count, F.nv, wtmax, sb.dps[i]) &&
-                    quad_supports_digits(sb.dps[i].D)) {
+                    (ctx.quad ? quad_supports_digits(sb.dps[i].D) : wide_supports_digits(sb.dps[i].D))) {
                     it.apack.resize((size_t)nrt * sb.dps[i].D * nkb * 1024);
                     if (!ctx.device_psi)
                         pack_psi_digits(F, it, sb.dps[i], nrt, nkb, it.apack.data(), &ctx.fe->ql);
@@ -675,7 +692,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     for (int li = 0; li < nlive && sb.use_mfma; li++) sb.use_mfma = sb.digit_ok[sb.live[li]] != 0;
     for (int li = 0; li < nlive && sb.use_mfma && sb.use_bins; li++)
         if (!mfma4_supports(df, sb.dps[sb.live[li]].D)) sb.use_mfma = false;  // packed for the other layout
-    if (sb.use_mfma && !sb.use_bins && !ctx.quad && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
+    if (sb.use_mfma && !sb.use_bins && !ctx.quad && !ctx.wide && policy != CR_POLICY_DEPTH_FIRST) sb.use_mfma = false;
     // tile pairs are chosen per digit count: the items whose digit count the
     // pair kernel takes get their psi digits folded, the others run on single tiles
     sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;
@@ -821,6 +838,11 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     if (sb.use_mfma && dpsi)
         for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     sb.o_queue = take(4 * std::max<size_t>(sb.launches.size(), 1));
+    if (sb.use_mfma && ctx.wide) {  // digit planes of the threefold kernel, per workgroup of the persistent grid
+        int dmax = 1;
+        for (int li = 0; li < nlive; li++) dmax = std::max(dmax, sb.dps[sb.live[li]].D);
+        sb.o_xw = take(wide_scratch_bytes(dmax, wide_grid(1 << 30, std::max(1, ctx.fam->grid))));
+    }
     sb.o_Y = take(8 * (size_t)b * b * nlive);
     const size_t o_H = take(8 * (size_t)F.fin.count * b * nlive);
     sb.o_hbuf = take(8 * (size_t)F.fin.count * nvec);
@@ -1012,7 +1034,9 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     uint64_t *storep = reinterpret_cast<uint64_t *>(db + sb.o_store);
     uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + sb.o_hbuf);
     int *errp = reinterpret_cast<int *>(db + sb.o_err);
-    const int mode = sb.use_mfma && (sb.use_bins || ctx.quad) ? ctx.fam->launch : 0;
+    // the threefold kernel always runs its persistent form (its digit planes are per workgroup)
+    const int mode = sb.use_mfma && ctx.wide ? std::max(1, ctx.fam->launch)
+                                             : (sb.use_mfma && (sb.use_bins || ctx.quad) ? ctx.fam->launch : 0);
     const int pgrid = mode > 0 ? std::max(1, ctx.fam->grid) : 0;  // persistent: workgroups per CU
     int *queue = reinterpret_cast<int *>(db + sb.o_queue);
     // the reduction phases (and the combines between them) on stream `rs`
@@ -1047,6 +1071,11 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                         e = launch_reduce_quad(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_qslots),
                                                errp, pgrid, queue + li, rs);
+                    else if (ctx.wide)
+                        e = launch_reduce_wide(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
+                                               reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_qslots),
+                                               errp, Dg, wide_grid(L.ntiles, pgrid),
+                                               reinterpret_cast<int8_t *>(db + sb.o_xw), queue + li, rs);
                     else if (L.pairs)
                         e = launch_reduce_mfma5(df, ditems, gt, L.ntiles, cu, cgp, cp, vxp, storep, hb64,
                                                 reinterpret_cast<const uint32_t *>(db + sb.o_tables + ctx.fe->off_slots),
@@ -1072,7 +1101,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
                    std::to_string(L.ntiles) + (L.pairs ? "p" : "s");
         for (int t = 0; t < sb.nphase; t++) sig += "/" + std::to_string(sb.comb_first[t]) + "," + std::to_string(sb.comb_count[t]);
         for (size_t o : {sb.o_items, sb.o_tiles, sb.o_ditems, sb.o_tables, sb.o_cu, sb.o_cg, sb.o_cp, sb.o_vx,
-                         sb.o_comb, sb.o_msrc, sb.o_malpha, sb.o_err, sb.o_hbuf, sb.o_store, sb.o_queue})
+                         sb.o_comb, sb.o_msrc, sb.o_malpha, sb.o_err, sb.o_hbuf, sb.o_store, sb.o_queue, sb.o_xw})
             sig += ";" + std::to_string(o);
         hipGraphExec_t exec = nullptr;
         auto f = g_graphs.find(sig);
@@ -1586,7 +1615,7 @@ cr_status frobenius_batch(const cr_family *fam, int32_t count, const int32_t *pr
             if (!sb.live.empty()) {
                 bool any_pairs = false;
                 for (auto &L : sb.launches) any_pairs = any_pairs || L.pairs;
-                const int e = sb.use_mfma ? (ctx.quad ? 4 : (any_pairs ? 0 : (sb.use_bins ? 3 : 2))) : 1;
+                const int e = sb.use_mfma ? (ctx.quad ? 4 : ctx.wide ? 5 : (any_pairs ? 0 : (sb.use_bins ? 3 : 2))) : 1;
                 // a sub-batch that fell back to the VALU kernel makes the call report it
                 if (stats->engine < 0 || e == 1) stats->engine = e;
             }

@@ -1043,6 +1043,51 @@ bool quad_layout(const Family &fam, int nrt, int nrtf, BinLayout &bl) {
     return true;
 }
 
+bool wide_layout(const Family &fam, int nrt, int nrtq, BinLayout &bl) {
+    const int s = fam.g.count, nv = fam.nv;
+    if (nv != 5 || nrtq > nrt) return false;
+    bl.nbins = 2 * nrt;
+    bl.slot_src.assign((size_t)bl.nbins * 16, -1);
+    bl.slot.assign((size_t)bl.nbins * 16, 0);
+    const int five_cap = nrtq * 2 * 3, single_cap = nrtq * 2 + (nrt - nrtq) * 2 * 16;
+    int nfive = 0, nsingle = 0;
+    for (int r = 0; r < s; r++) {
+        int members[5], cnt = 0;
+        for (int i = 0; i < nv; i++)
+            if (fam.gsrc[(size_t)r * nv + i] >= 0) members[cnt++] = i;
+        if (cnt == 0) continue;
+        int bin, j0;
+        if (cnt == 5) {
+            if (nfive >= five_cap) return false;
+            bin = nfive / 3;
+            j0 = (nfive % 3) * 5;
+            nfive++;
+        } else if (cnt == 1) {
+            if (nsingle >= single_cap) return false;
+            if (nsingle < nrtq * 2) {
+                bin = nsingle;
+                j0 = 15;
+            } else {
+                const int t = nsingle - nrtq * 2;
+                bin = 2 * nrtq + t / 16;
+                j0 = t % 16;
+            }
+            nsingle++;
+        } else {
+            return false;
+        }
+        for (int m = 0; m < cnt; m++) {
+            const int i = members[m], j = cnt == 5 ? j0 + i : j0;  // five-source slot 5 q + i is variable i
+            bl.slot_src[(size_t)bin * 16 + j] = fam.gsrc[(size_t)r * nv + i];
+            bl.slot[(size_t)bin * 16 + j] =
+                1u | ((uint32_t)i << 2) | ((uint32_t)fam.gw[(size_t)r * nv + i] << 5) | ((uint32_t)r << 16);
+        }
+    }
+    // an unused five-source group is marked r = 0xFFFF in its first slot
+    for (int q = nfive; q < five_cap; q++) bl.slot[(size_t)(q / 3) * 16 + (q % 3) * 5] = 0xFFFFu << 16;
+    return true;
+}
+
 bool quad_digit_params(int p, int M, int T, int nv, u64 wtmax, DigitParams &dp) {
     int e = 1;
     while ((long long)std::llround(std::pow((double)p, e + 1)) <= 169) e++;

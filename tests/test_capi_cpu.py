@@ -89,7 +89,7 @@ def test_bad_prime_statuses_without_device():
 
 def test_family_options_are_validated():
     items = [(31, [1] * 21)]
-    for kw in ({"launch": 3}, {"policy": 7}, {"engine": 5},
+    for kw in ({"launch": 3}, {"policy": 7}, {"engine": 6},
                {"engine": C.ENGINE_MFMA_LDS, "policy": C.CR_POLICY_P_CHUNK}):
         with pytest.raises(C.CrError) as e:
             C.cr_frobenius_batch(C.family(3, 5, **kw), [p for p, _ in items], [c for _, c in items])

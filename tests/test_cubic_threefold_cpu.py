@@ -8,10 +8,9 @@ of the oracle: the functional equation and the Weil bound for weight 3, and
 eigenvalues).  Its Newton invariants (Section 6.5: p-rank = length of the
 slope-1 segment) agree between the library's host routine and the oracle.
 
-The library has no device path for this family: the right inverse of J_S
-has 1.8 million entries, beyond the 64-bit kernel's table, and no MFMA
-kernel covers five variables of degree 3; cr_frobenius_batch refuses it with
-CR_EINVAL instead of falling back to anything.
+On the GPU the threefold kernel (int8-digit MFMA over the 1815 x 1001 right
+inverse of J_S) reproduces the stored result bit for bit; cubic fourfolds,
+which no kernel covers, are refused with CR_EINVAL.
 """
 import json
 import os
@@ -89,9 +88,32 @@ def test_newton_invariants_library_matches_oracle():
 
 
 @pytest.mark.gpu
-def test_gpu_refuses_family_without_device_path():
+def test_gpu_threefold_kernel_matches_golden():
+    """The threefold kernel (engine 5, int8-digit MFMA, 57 row tiles x 32
+    K-blocks) against the oracle's stored result, bit for bit: the scaled
+    matrix mod p^M, Phi' mod p^(column precision), column poles and
+    precisions, and Q(T)."""
     g = golden()
-    fam = C.family(5, 3, s_mask=1 << 4)
+    for policy in (C.CR_POLICY_DEPTH_FIRST, C.CR_POLICY_P_CHUNK):
+        fam = C.family(5, 3, s_mask=1 << 4, policy=policy)
+        res = C.cr_frobenius_batch(fam, [g["p"]], [g["coeffs"]])
+        assert res["stats"].engine == C.ENGINE_WIDE and res["stats"].policy == policy
+        assert [[int(x) for x in row] for row in res["scaled"][0]] == [[int(x) for x in row] for row in g["scaled"]]
+        assert [int(x) for x in res["col_pole"][0]] == g["col_pole"]
+        assert [int(x) for x in res["col_prec"][0]] == g["col_prec"]
+        prec = g["col_prec"]
+        want = [[int(x) % g["p"] ** prec[c] for c, x in enumerate(row)] for row in g["phi_prime"]]
+        assert [[int(x) for x in row] for row in res["frob"][0]] == want
+        assert res["lpoly"][0] == [int(x) for x in g["lpoly"]]
+
+
+@pytest.mark.gpu
+def test_gpu_refuses_family_without_device_path():
+    """Cubic fourfolds (six variables, S = {x_5}): psi has 80 million entries
+    and no MFMA kernel covers the family, so the call is refused before any
+    setup (the coefficients are not even looked at)."""
+    fam = C.family(6, 3, s_mask=1 << 5)
+    nco, _s, _b = C.cr_query_dims(6, 3)
     with pytest.raises(C.CrError, match="no device path") as e:
-        C.cr_frobenius_batch(fam, [g["p"]], [g["coeffs"]])
+        C.cr_frobenius_batch(fam, [7], [[1] * nco])
     assert e.value.status == C.CR_EINVAL
