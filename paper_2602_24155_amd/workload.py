@@ -48,6 +48,7 @@ WORKLOADS = {
     "cubic_fourfold_f7": Workload(5, "cubic_fourfold_f7", 6, 3, (7,), 1, s_mask=1 << 5),
     "sparse_k3_mixed": Workload(7, "sparse_k3_mixed", 4, 4, (7, 11, 13), 64, extra_terms=2),
     "cubic_threefold_f7": Workload(8, "cubic_threefold_f7", 5, 3, (7,), 1, s_mask=1 << 4),
+    "cubic_threefolds_mixed": Workload(9, "cubic_threefolds_mixed", 5, 3, (7, 11), 16, s_mask=1 << 4),
 }
 
 

@@ -108,6 +108,31 @@ def test_gpu_threefold_kernel_matches_golden():
 
 
 @pytest.mark.gpu
+def test_gpu_threefold_batch_properties():
+    """A batch of random cubic threefolds over F_7 and F_11 (the second prime
+    of Section 5.3's example) with the golden threefold among them: every
+    Q(T) satisfies the functional equation and the Weil bound in weight 3
+    and gives #X(F_p) by brute force; the golden item is bit-exact."""
+    fam = C.family(5, 3, s_mask=1 << 4)
+    items = [workload.first_accepted("cubic_threefolds_mixed", j, lambda p, c: C.cr_check_smooth(fam, p, c))
+             for j in range(6)]
+    g = golden()
+    items.insert(3, (g["p"], g["coeffs"]))
+    assert {p for p, _ in items} == {7, 11}
+    res = C.cr_frobenius_batch(fam, [p for p, _ in items], [c for _, c in items])
+    assert res["stats"].engine == C.ENGINE_WIDE
+    for i, (p, c) in enumerate(items):
+        assert res["item_status"][i] == C.CR_OK
+        a = res["lpoly"][i]
+        assert len(a) == 11 and a[0] == 1 and abs(a[10]) == p ** 15
+        assert weil_root_check_squarefree(a, p, 3)
+        f = {e: v % p for e, v in from_coeffs(5, 3, c).items() if v % p}
+        assert point_counts_from_lpoly(a, p, 4, 1) == [count_projective(f, 5, p, 1)]
+    assert [[int(x) for x in row] for row in res["scaled"][3]] == [[int(x) for x in row] for row in g["scaled"]]
+    assert res["lpoly"][3] == [int(x) for x in g["lpoly"]]
+
+
+@pytest.mark.gpu
 def test_gpu_refuses_family_without_device_path():
     """Cubic fourfolds (six variables, S = {x_5}): psi has 80 million entries
     and no MFMA kernel covers the family, so the call is refused before any
