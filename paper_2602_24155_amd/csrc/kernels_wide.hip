@@ -12,8 +12,9 @@
 // digits nor the vectors' digit planes (D x 32 x 1040 bytes per set, twice
 // the LDS) stay on chip.  Each workgroup keeps its two plane sets in a slice
 // of global memory (L2-resident; only the family tables are in LDS) and every
-// wave streams psi's digit fragments and the planes' fragments for each of
-// its row tiles, one K-block ahead.  All waves of a workgroup run on one CU,
+// wave takes its row tiles two at a time, streaming psi's digit fragments of
+// both and the planes' fragments once for the two, one K-block ahead.  All
+// waves of a workgroup run on one CU,
 // so the workgroup barrier orders their writes and reads of the planes as it
 // does for LDS.
 //
@@ -183,6 +184,85 @@ __device__ __forceinline__ void products(const v4i (&a)[D], const v4i (&x)[D], v
             acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], x[j], acc[i + j], 0, 0, 0);
 }
 
+// Products of row tiles rt and (TWO) rt2 with the current planes over all
+// K-blocks, in pairs of K-blocks with two fragment buffers: the loads of the
+// next block are in flight during the products of this one.
+template <int D, int NKB, int XS, bool TWO>
+__device__ __forceinline__ void pair_products(const int8_t *abase, const int8_t *xbase, int rt, int rt2,
+                                              v16i (&acc)[D], v16i (&acc2)[D]) {
+    v4i a0[D], b0[D], x0[D], a1[D], b1[D], x1[D];
+    load_a<D, NKB>(abase, rt, 0, a0);
+    if (TWO) load_a<D, NKB>(abase, rt2, 0, b0);
+    load_x<D, XS>(xbase, 0, x0);
+    for (int kb = 0; kb < NKB; kb += 2) {
+        load_a<D, NKB>(abase, rt, kb + 1, a1);
+        if (TWO) load_a<D, NKB>(abase, rt2, kb + 1, b1);
+        load_x<D, XS>(xbase, kb + 1, x1);
+        products<D>(a0, x0, acc);
+        if (TWO) products<D>(b0, x0, acc2);
+        if (kb + 2 < NKB) {
+            load_a<D, NKB>(abase, rt, kb + 2, a0);
+            if (TWO) load_a<D, NKB>(abase, rt2, kb + 2, b0);
+            load_x<D, XS>(xbase, kb + 2, x0);
+        }
+        products<D>(a1, x1, acc);
+        if (TWO) products<D>(b1, x1, acc2);
+    }
+}
+
+// The outputs of row tile rt held by this lane half: in a quint tile three
+// five-source outputs (slots 5 qd + i, variable i) and one one-source output
+// (slot 15), past the quint tiles sixteen one-source outputs.
+template <int NRTQ, int D, int XS>
+__device__ __forceinline__ void finish_rt(int rt, int half, const v16i (&acc)[D], const uint32_t *slotL,
+                                          const int (&up)[kWNV], bool more, const int16_t *cm, int8_t *Xn_c, int vout,
+                                          int fin_row, const int16_t *__restrict__ finmap, uint64_t *hrow,
+                                          uint64_t *__restrict__ store, int s, double Bd, double invB, int64_t Bi,
+                                          int64_t q, double invq, int &bad) {
+    const uint32_t *sb = slotL + (rt * 2 + half) * 16;
+    if (rt < NRTQ) {
+#pragma unroll
+        for (int qd = 0; qd < 3; qd++) {
+            const uint32_t w0 = sb[5 * qd];
+            const int r = (int)(w0 >> 16);
+            if (r == 0xFFFF) continue;
+            double z[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) z[k] = 0.0;
+#pragma unroll
+            for (int t = 0; t < kWNV; t++) {
+                const double wt = (double)(up[t] + (int)((sb[5 * qd + t] >> 5) & 2047u));
+#pragma unroll
+                for (int k = 0; k < D; k++) z[k] = fma(wt, (double)acc[k][5 * qd + t], z[k]);
+            }
+            emit_w<D, XS>(z, r, more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi, q, invq, bad);
+        }
+        const uint32_t w = sb[15];
+        if (w & 1u) {
+            const int iv = (int)((w >> 2) & 7u);
+            const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
+            double z[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][15];
+            emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi, q,
+                          invq, bad);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const uint32_t w = sb[j];
+            if (!(w & 1u)) continue;
+            const int iv = (int)((w >> 2) & 7u);
+            const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
+            double z[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][j];
+            emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi, q,
+                          invq, bad);
+        }
+    }
+}
+
 // One tile (up to 32 vectors of one item) on the workgroup's plane sets X
 // (global memory, 2 XB bytes).
 template <int NRT, int NRTQ, int NKB, int D>
@@ -302,71 +382,23 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
 
         const int8_t *abase = it.apack + lane * 16;
         const int8_t *xbase = Xc + c * XS + half * 16;
-        for (int rt = wave; rt < NRT; rt += kWWaves) {
-            v16i acc[D];
+        // row tiles in pairs (rt, rt + 4): one stream of the planes' fragments
+        // feeds the products of both, which halves the plane reads
+        for (int rt = wave; rt < NRT; rt += 2 * kWWaves) {
+            const int rt2 = rt + kWWaves;
+            v16i acc[D], acc2[D];
 #pragma unroll
-            for (int k = 0; k < D; k++) acc[k] = v16i{0};
-            // K-blocks in pairs with two fragment buffers: the loads of the
-            // next block are in flight during the products of this one
-            v4i a0[D], x0[D], a1[D], x1[D];
-            load_a<D, NKB>(abase, rt, 0, a0);
-            load_x<D, XS>(xbase, 0, x0);
-            for (int kb = 0; kb < NKB; kb += 2) {
-                load_a<D, NKB>(abase, rt, kb + 1, a1);
-                load_x<D, XS>(xbase, kb + 1, x1);
-                products<D>(a0, x0, acc);
-                if (kb + 2 < NKB) {
-                    load_a<D, NKB>(abase, rt, kb + 2, a0);
-                    load_x<D, XS>(xbase, kb + 2, x0);
-                }
-                products<D>(a1, x1, acc);
-            }
+            for (int k = 0; k < D; k++) acc[k] = acc2[k] = v16i{0};
+            if (rt2 < NRT)
+                pair_products<D, NKB, XS, true>(abase, xbase, rt, rt2, acc, acc2);
+            else
+                pair_products<D, NKB, XS, false>(abase, xbase, rt, rt, acc, acc2);
             if (!act) continue;
-            const uint32_t *sb = slotL + (rt * 2 + half) * 16;
-            if (rt < NRTQ) {
-                // three five-source outputs (slots 5 qd + i, variable i), then one one-source output (slot 15)
-#pragma unroll
-                for (int qd = 0; qd < 3; qd++) {
-                    const uint32_t w0 = sb[5 * qd];
-                    const int r = (int)(w0 >> 16);
-                    if (r == 0xFFFF) continue;
-                    double z[D];
-#pragma unroll
-                    for (int k = 0; k < D; k++) z[k] = 0.0;
-#pragma unroll
-                    for (int t = 0; t < kWNV; t++) {
-                        const double wt = (double)(up[t] + (int)((sb[5 * qd + t] >> 5) & 2047u));
-#pragma unroll
-                        for (int k = 0; k < D; k++) z[k] = fma(wt, (double)acc[k][5 * qd + t], z[k]);
-                    }
-                    emit_w<D, XS>(z, r, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s, Bd, invB, Bi, q,
-                                  invq, bad);
-                }
-                const uint32_t w = sb[15];
-                if (w & 1u) {
-                    const int iv = (int)((w >> 2) & 7u);
-                    const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
-                    double z[D];
-#pragma unroll
-                    for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][15];
-                    emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s, Bd,
-                                  invB, Bi, q, invq, bad);
-                }
-            } else {
-                // sixteen one-source outputs
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const uint32_t w = sb[j];
-                    if (!(w & 1u)) continue;
-                    const int iv = (int)((w >> 2) & 7u);
-                    const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
-                    double z[D];
-#pragma unroll
-                    for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][j];
-                    emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s, Bd,
-                                  invB, Bi, q, invq, bad);
-                }
-            }
+            finish_rt<NRTQ, D, XS>(rt, half, acc, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s,
+                                   Bd, invB, Bi, q, invq, bad);
+            if (rt2 < NRT)
+                finish_rt<NRTQ, D, XS>(rt2, half, acc2, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow,
+                                       store, s, Bd, invB, Bi, q, invq, bad);
         }
         __syncthreads();  // every wave has read the current planes and written the next ones
         int8_t *Xz = X + cur * XB;
