@@ -104,6 +104,14 @@ __device__ __forceinline__ void load_frags(const int8_t *base, int rt, int kb, v
     for (int i = 0; i < D; i++) dst[i] = *(gv4i *)(base + (((size_t)rt * D + i) * NKB + kb) * 1024);
 }
 
+// Fragments of digit planes 0..D-1 of K-block kb (LDS); xc = this lane's
+// vector row plus its 16-byte half.
+template <int D, int XS>
+__device__ __forceinline__ void load_planes(const int8_t *xc, int kb, v4i (&dst)[D]) {
+#pragma unroll
+    for (int j = 0; j < D; j++) dst[j] = *reinterpret_cast<const v4i *>(xc + (size_t)j * kQV * XS + kb * 32);
+}
+
 // Balanced base-B digits of x in [0, q) (q | Q'), written D planes apart.
 // v < Q' < 2^52 is exact in fp64: the quotient by B from the product with
 // 1 / B is off by at most one, which the remainder's range corrects (a 64-bit
@@ -292,31 +300,42 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
         int8_t *Xn_c = Xn + c * XS;
         uint64_t *hrow = hbuf + (size_t)(tile.chain0 + c) * F;
 
-        // psi digit fragments one K-block ahead (and the next row tile's first
-        // block during the finish): one wave per SIMD has no other wave to hide
-        // the latency of the loads from L2
+        // psi digit fragments (L2) and plane fragments (LDS) one K-block ahead,
+        // and the next row tile's first psi block during the last block and
+        // the finish: one wave per SIMD has no other wave to hide the latency
+        // of the loads.  The scheduling fences keep each block's loads ahead
+        // of its products; without them the compiler sinks the loads to their
+        // uses under register pressure, and every fragment waits for its load.
         const int8_t *abase = it.apack + lane * 16;
-        v4i an[D];
+        const int8_t *xbase = Xc + c * XS + half * 16;
+        v4i an[D], xn[D];
         if (wave < NRT) load_frags<D, NKB>(abase, wave, 0, an);
         for (int rt = wave; rt < NRT; rt += kQWaves) {
             v16i acc[D];
 #pragma unroll
             for (int k = 0; k < D; k++) acc[k] = v16i{0};
+            load_planes<D, XS>(xbase, 0, xn);
 #pragma unroll
             for (int kb = 0; kb < NKB; kb++) {
                 v4i xb[D], a[D];
 #pragma unroll
-                for (int i = 0; i < D; i++) a[i] = an[i];
-                if (kb + 1 < NKB) load_frags<D, NKB>(abase, rt, kb + 1, an);
-                else if (rt + kQWaves < NRT) load_frags<D, NKB>(abase, rt + kQWaves, 0, an);
-#pragma unroll
-                for (int j = 0; j < D; j++)
-                    xb[j] = *reinterpret_cast<const v4i *>(Xc + (j * kQV + c) * XS + kb * 32 + half * 16);
+                for (int i = 0; i < D; i++) {
+                    a[i] = an[i];
+                    xb[i] = xn[i];
+                }
+                if (kb + 1 < NKB) {
+                    load_frags<D, NKB>(abase, rt, kb + 1, an);
+                    load_planes<D, XS>(xbase, kb + 1, xn);
+                } else if (rt + kQWaves < NRT) {
+                    load_frags<D, NKB>(abase, rt + kQWaves, 0, an);
+                }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < D; i++)
 #pragma unroll
                     for (int j = 0; i + j < D; j++)
                         acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], xb[j], acc[i + j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (!act) continue;
             const uint32_t *sb = slotL + (rt * 2 + half) * 16;
