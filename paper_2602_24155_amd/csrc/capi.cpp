@@ -722,7 +722,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     std::vector<int> gkey(nlive, 0), dvals;
     for (int li = 0; li < nlive; li++)
         if (sb.use_mfma && !ctx.quad)  // the quad kernel takes every digit count in one launch
-            gkey[li] = sb.dps[sb.live[li]].D + 100 * sb.dps[sb.live[li]].z32;
+            gkey[li] = sb.dps[sb.live[li]].D + (ctx.wide ? 0 : 100 * sb.dps[sb.live[li]].z32);
     dvals = gkey;
     std::sort(dvals.begin(), dvals.end());
     dvals.erase(std::unique(dvals.begin(), dvals.end()), dvals.end());

@@ -1104,6 +1104,8 @@ bool quad_digit_params(int p, int M, int T, int nv, u64 wtmax, DigitParams &dp) 
     const long double tmax = ((long double)nv * (long double)wtmax * Smax + 0.5L) * B / (long double)(B - 1);
     if (tmax >= std::ldexp(1.0L, 48)) return false;
     dp = DigitParams();
+    // int32 finish: accumulators within 24-bit multiplies and the carry sums within int32
+    dp.z32 = Smax < std::ldexp(1.0L, 23) - 1 && tmax < std::ldexp(1.0L, 31) - 1 ? 1 : 0;
     dp.e = e;
     dp.B = (int)B;
     dp.D = D;

@@ -136,24 +136,13 @@ __device__ __forceinline__ void put_digits_q(int8_t *xp, uint64_t x, uint64_t Qp
     }
 }
 
-// Output r of vector c from its weighted position sums z[0..D-1]: carry
-// propagation to balanced digits, then either the digits of the next step or
-// the final value mod q (combine store or pole-n numerators).
+// Output r of vector c from its balanced digits dg[0..D-1] (the carry
+// propagation over its weighted position sums): either the digits of the
+// next step or the final value mod q (combine store or pole-n numerators).
 template <int D, int XS>
-__device__ __forceinline__ void emit_q(const double (&z)[D], int r, bool more, const int16_t *cm, int8_t *Xn_c,
-                                       int vout, int fin_row, const int16_t *__restrict__ finmap, uint64_t *hrow,
-                                       uint64_t *__restrict__ store, int s, double Bd, double invB, int64_t Bi,
-                                       int64_t q, int &bad) {
-    int dg[D];
-    double carry = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; k++) {
-        const double t = z[k] + carry;
-        const double cq = rint(t * invB);
-        dg[k] = (int)fma(-cq, Bd, t);
-        carry = cq;
-    }
-    // the carry out of position D - 1 is a multiple of Q' and is dropped
+__device__ __forceinline__ void put_out_q(const int (&dg)[D], int r, bool more, const int16_t *cm, int8_t *Xn_c,
+                                          int vout, int fin_row, const int16_t *__restrict__ finmap, uint64_t *hrow,
+                                          uint64_t *__restrict__ store, int s, int64_t Bi, int64_t q, int &bad) {
     if (more) {
         const int col = cm[r];
         if (col < 0) {
@@ -185,8 +174,107 @@ __device__ __forceinline__ void emit_q(const double (&z)[D], int r, bool more, c
     }
 }
 
-template <int NRT, int NRTF, int NKB, int D>
-__device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDigitItem *__restrict__ items,
+// Four outputs of this lane half of a row tile: their weighted position
+// sums z_k, then their carry propagations side by side, position by position
+// (four independent chains in flight instead of one), then their digits out.
+// FULL: the row tile's four full quads, one output each (quad o, its rows
+// 4 o + t with weights of variable t); else the four one-row outputs of
+// single quad qd (row 4 qd + t, variable t).
+//
+// Z32 (the host has bounded |acc| < 2^23 and |t_k| < 2^31 for the item): the
+// sums are 24-bit multiply-adds in int32 and carry = round(t / B) is the low
+// word of t / B + 1.5 2^52 in fp64 (for |t| < 2^31 the product's error, below
+// 2^-22, cannot carry t / B across a half-integer, which it lies at least
+// 1 / (2B) from); the digit t - B carry is only needed mod 2^8 (|d| < 128),
+// where a 24-bit multiply-add gives it.  Otherwise fp64 throughout: |t_k| <
+// 2^48 (checked on the host) keeps t * (1/B) within |t| 2^-52 / B of t / B,
+// so rint gives the exact quotient.
+template <int D, int XS, bool FULL, bool Z32>
+__device__ __forceinline__ void finish4(const v16i (&acc)[D], int qd, const uint32_t *sb, const int (&up)[4],
+                                        bool more, const int16_t *cm, int8_t *Xn_c, int vout, int fin_row,
+                                        const int16_t *__restrict__ finmap, uint64_t *hrow,
+                                        uint64_t *__restrict__ store, int s, double Bd, double invB, int Bs,
+                                        int64_t Bi, int64_t q, int &bad) {
+    int wt[4][4];
+    int rr[4];
+    bool ok[4];
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+        if (FULL) {
+            rr[o] = (int)(sb[4 * o] >> 16);
+            ok[o] = rr[o] != 0xFFFF;
+#pragma unroll
+            for (int t = 0; t < 4; t++) wt[o][t] = up[t] + (int)((sb[4 * o + t] >> 5) & 2047u);
+        } else {
+            const uint32_t w = sb[4 * qd + o];
+            rr[o] = (int)(w >> 16);
+            ok[o] = (w & 1u) != 0;
+            wt[o][0] = up[o] + (int)((w >> 5) & 2047u);
+        }
+    }
+    int dg[4][D];
+    if constexpr (Z32) {
+        constexpr double kRound = 6755399441055744.0;  // 1.5 2^52
+        int ci[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < D; k++)
+#pragma unroll
+            for (int o = 0; o < 4; o++) {
+                int t = ci[o];
+                if (FULL) {
+#pragma unroll
+                    for (int m = 0; m < 4; m++) t = __mul24(wt[o][m], acc[k][4 * o + m]) + t;
+                } else {
+                    t = __mul24(wt[o][0], acc[k][4 * qd + o]) + t;
+                }
+                ci[o] = __double2loint(fma((double)t, invB, kRound));
+                // low 24 bits of the carry times 2^24 - B, plus t: = d_k mod 2^8
+                unsigned du;
+                asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(du) : "v"(ci[o]), "v"((1u << 24) - (unsigned)Bs), "v"(t));
+                dg[o][k] = (int)(int8_t)(du & 0xffu);
+            }
+    } else {
+        double z[4][D];
+#pragma unroll
+        for (int o = 0; o < 4; o++) {
+#pragma unroll
+            for (int k = 0; k < D; k++) z[o][k] = 0.0;
+            if (FULL) {
+#pragma unroll
+                for (int m = 0; m < 4; m++)
+#pragma unroll
+                    for (int k = 0; k < D; k++) z[o][k] = fma((double)wt[o][m], (double)acc[k][4 * o + m], z[o][k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; k++) z[o][k] = (double)wt[o][0] * (double)acc[k][4 * qd + o];
+            }
+        }
+        double carry[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < D; k++)
+#pragma unroll
+            for (int o = 0; o < 4; o++) {
+                const double v = z[o][k] + carry[o];
+                const double cq = rint(v * invB);
+                dg[o][k] = (int)fma(-cq, Bd, v);
+                carry[o] = cq;
+            }
+    }
+    // the carry out of position D - 1 is a multiple of Q' and is dropped.
+    // The digits are pinned here: the compiler would otherwise sink each
+    // output's whole chain into the branch that writes it, one chain after
+    // the other again.
+#pragma unroll
+    for (int o = 0; o < 4; o++)
+#pragma unroll
+        for (int k = 0; k < D; k++) asm volatile("" : "+v"(dg[o][k]));
+#pragma unroll
+    for (int o = 0; o < 4; o++)
+        if (ok[o]) put_out_q<D, XS>(dg[o], rr[o], more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bi, q, bad);
+}
+
+template <int NRT, int NRTF, int NKB, int D, bool Z32>
+__device__ __forceinline__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDigitItem *__restrict__ items,
                           const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                           const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
                           uint64_t *__restrict__ store, uint64_t *__restrict__ hbuf, int &bad, int8_t *Xbuf,
@@ -340,39 +428,15 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
             if (!act) continue;
             const uint32_t *sb = slotL + (rt * 2 + half) * 16;
             if (rt < NRTF) {
-                // full quads: one output, sources of variables 0..3 in slots 0..3
-#pragma unroll
-                for (int qd = 0; qd < 4; qd++) {
-                    const uint32_t w0 = sb[4 * qd];
-                    const int r = (int)(w0 >> 16);
-                    if (r == 0xFFFF) continue;
-                    double z[D];
-#pragma unroll
-                    for (int k = 0; k < D; k++) z[k] = 0.0;
-#pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const double wt = (double)(up[t] + (int)((sb[4 * qd + t] >> 5) & 2047u));
-#pragma unroll
-                        for (int k = 0; k < D; k++) z[k] = fma(wt, (double)acc[k][4 * qd + t], z[k]);
-                    }
-                    emit_q<D, XS>(z, r, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s, Bd, invB, Bi, q,
-                                  bad);
-                }
+                // full quads: one output each, sources of variables 0..3 in slots 0..3
+                finish4<D, XS, true, Z32>(acc, 0, sb, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s,
+                                          Bd, invB, it.B, Bi, q, bad);
             } else {
                 // single quads: four one-row outputs, slot t of variable t
 #pragma unroll
                 for (int qd = 0; qd < 4; qd++)
-#pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const uint32_t w = sb[4 * qd + t];
-                        if (!(w & 1u)) continue;
-                        const double wt = (double)(up[t] + (int)((w >> 5) & 2047u));
-                        double z[D];
-#pragma unroll
-                        for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][4 * qd + t];
-                        emit_q<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s,
-                                      Bd, invB, Bi, q, bad);
-                    }
+                    finish4<D, XS, false, Z32>(acc, qd, sb, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow,
+                                               store, s, Bd, invB, it.B, Bi, q, bad);
             }
         }
         __syncthreads();  // every wave has read the current planes and written the next ones
@@ -393,8 +457,9 @@ __device__ void quad_tile(const DevFamily &fam, const DevTile &tile, const DevDi
     }
 }
 
-// One tile with the digit count of its item: DLO or DHI (the hypersurfaces
-// of one call may have different primes, hence different digit counts; one
+// One tile with the digit count of its item, DLO or DHI, and its finish
+// arithmetic, int32 where the item's bounds allow it (the hypersurfaces of
+// one call may have different primes, hence different digit counts; one
 // launch takes the tiles of all of them).
 template <int NRT, int NRTF, int NKB, int DLO, int DHI>
 __device__ __forceinline__ void quad_tile_any(const DevFamily &fam, const DevTile &tile,
@@ -405,12 +470,22 @@ __device__ __forceinline__ void quad_tile_any(const DevFamily &fam, const DevTil
                                               const int16_t *colmapL, const int8_t *dirsL, const int8_t *finUL,
                                               const uint32_t *slotL) {
     const int D = __builtin_amdgcn_readfirstlane(items[tile.item].D);
-    if (D == DLO)
-        quad_tile<NRT, NRTF, NKB, DLO>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL, dirsL,
-                                       finUL, slotL);
-    else
-        quad_tile<NRT, NRTF, NKB, DHI>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL, dirsL,
-                                       finUL, slotL);
+    const int z32 = __builtin_amdgcn_readfirstlane(items[tile.item].z32);
+    if (D == DLO) {
+        if (z32)
+            quad_tile<NRT, NRTF, NKB, DLO, true>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL,
+                                                 dirsL, finUL, slotL);
+        else
+            quad_tile<NRT, NRTF, NKB, DLO, false>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL,
+                                                  dirsL, finUL, slotL);
+    } else {
+        if (z32)
+            quad_tile<NRT, NRTF, NKB, DHI, true>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL,
+                                                 dirsL, finUL, slotL);
+        else
+            quad_tile<NRT, NRTF, NKB, DHI, false>(fam, tile, items, cu, cg, cpole, vx, store, hbuf, bad, Xbuf, colmapL,
+                                                  dirsL, finUL, slotL);
+    }
 }
 
 // One workgroup per tile (queue == nullptr) or a persistent grid draining the
