@@ -52,10 +52,30 @@ def limbs_for(q):
 
 
 def _oracle_one(args):
-    nv, d, p, c, s_mask = args
+    nv, d, p, c, s_mask, r, n_series = args
     from oracle.frobenius import frobenius
-    frobenius(nv, d, p, c, S=[i for i in range(nv) if (s_mask >> i) & 1] if s_mask else None)
+    # under a precision override Q(T) is out of reach: the Frobenius matrix only
+    frobenius(nv, d, p, c, S=[i for i in range(nv) if (s_mask >> i) & 1] if s_mask else None,
+              r=r or None, N=n_series or None, lpoly=not r)
     return 1
+
+
+def wfamily(C, w, **kw):
+    """The library family of workload w (its S and precision overrides)."""
+    return C.family(w.nvars, w.degree, w.s_mask, r=w.r, n_series=w.n_series, **kw)
+
+
+def run_batch(C, w, fam, primes, coeffs, stream):
+    """One cr_frobenius_batch call; every item must succeed, except that under
+    a precision override Q(T) may be out of reach (CR_EPRECISION: the
+    Frobenius matrix is still computed)."""
+    res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False,
+                               raise_on_error=False)
+    allowed = (C.CR_OK, C.CR_EPRECISION) if w.r else (C.CR_OK,)
+    bad = [(i, int(x)) for i, x in enumerate(res["item_status"]) if int(x) not in allowed]
+    if bad or (res["status"] not in allowed):
+        raise C.CrError(res["status"], "items failed: %s" % bad[:8])
+    return res
 
 
 def host_info():
@@ -89,7 +109,8 @@ def cpu_baseline(name, items, budget_s=20.0):
     t = time.perf_counter()
     pool = ctx.Pool(1)
     try:
-        pool.apply_async(_oracle_one, ((w.nvars, w.degree, items[0][0], items[0][1], w.s_mask),)).get(timeout=3 * budget_s)
+        pool.apply_async(_oracle_one, ((w.nvars, w.degree, items[0][0], items[0][1], w.s_mask, w.r,
+                                             w.n_series),)).get(timeout=3 * budget_s)
     except mp.TimeoutError:
         pool.terminate()
         out = {"value": None, "unit": "frobenius_matrices/s", "cores": 1, "kind": "oracle",
@@ -102,7 +123,7 @@ def cpu_baseline(name, items, budget_s=20.0):
     per = time.perf_counter() - t
     n = max(cores, min(len(items), int(cores * budget_s / max(per, 1e-3))))
     n = min(n, len(items))
-    sample = [(w.nvars, w.degree, p, c, w.s_mask) for p, c in items[:n]]
+    sample = [(w.nvars, w.degree, p, c, w.s_mask, w.r, w.n_series) for p, c in items[:n]]
     t = time.perf_counter()
     with ctx.Pool(min(cores, n)) as pool:
         done = sum(pool.map(_oracle_one, sample, chunksize=1))
@@ -119,17 +140,25 @@ def plain_leg(C, w, items, sample, stream):
     """The per-hypersurface path on the GPU: one cr_frobenius call per item
     (64-bit VALU kernel, depth-first policy), over the first `sample` items."""
     import torch
-    fam = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_DEPTH_FIRST, engine=C.ENGINE_VALU)
+    fam = wfamily(C, w, policy=C.CR_POLICY_DEPTH_FIRST, engine=C.ENGINE_VALU)
     sub = items[:sample]
+    allowed = (C.CR_OK, C.CR_EPRECISION) if w.r else (C.CR_OK,)
+
+    def one(p, c):
+        res = C.cr_frobenius(fam, p, c, stream=stream, want_scaled=False, raise_on_error=False)
+        if res["status"] not in allowed:
+            raise C.CrError(res["status"], C.lib().cr_last_error().decode())
+        return res
+
     try:
-        C.cr_frobenius(fam, sub[0][0], sub[0][1], stream=stream, want_scaled=False)  # warm up
+        one(sub[0][0], sub[0][1])  # warm up
     except C.CrError as e:  # families the 64-bit kernel does not take (cubic threefolds)
         return {"value": None, "unit": "frobenius_matrices/s", "note": str(e)}
     torch.cuda.synchronize()
     t = time.perf_counter()
     steps = 0
     for p, c in sub:
-        steps += C.cr_frobenius(fam, p, c, stream=stream, want_scaled=False)["stats"].column_steps
+        steps += one(p, c)["stats"].column_steps
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     return {"value": len(sub) / wall, "unit": "frobenius_matrices/s", "ms_per_matrix": wall / len(sub) * 1e3,
@@ -137,38 +166,52 @@ def plain_leg(C, w, items, sample, stream):
             "engine": "k_reduce_chains (64-bit VALU)", "policy": "depth-first"}
 
 
-def learned_leg(C, w, fam0, items, primes, coeffs, stream, steps):
+# workloads whose network is trained on the traces of other families: the
+# quintic surfaces use a network trained on plane quartics, plane quintics and
+# quartic K3 surfaces only
+TRAIN_FROM = {"quintic_surfaces_r8": ("quartic_curve_f7", "quintic_curves_mixed", "quartic_k3_mixed")}
+
+
+def learned_leg(C, w, fam0, items, primes, coeffs, stream, steps, train_from=None):
     """The learned policy on the same batch: the network is trained on the GPU
-    (cr_mlp_train) from the plain p-chunk traces of 8 other items of the
-    workload, then the batch is reduced under CR_POLICY_LEARNED (judged by the
-    game cost against depth-first and p-chunk; the bits are unchanged)."""
+    (cr_mlp_train) from the plain p-chunk traces of 8 other items (of the
+    workload, or of the families TRAIN_FROM names), then the batch is reduced
+    under CR_POLICY_LEARNED (judged by the game cost against depth-first and
+    p-chunk; the bits are unchanged)."""
     import numpy as np
     import torch
     from paper_2602_24155_amd import workload
-    famc = C.family(w.nvars, w.degree, w.s_mask)
-    train = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(famc, p, c))
-             for j in range(w.count, w.count + 8)]
-    xs, ts = zip(*[C.cr_trace_policy(famc, p, c) for p, c in train])
+    sources = [workload.WORKLOADS[n] for n in (train_from or TRAIN_FROM.get(w.name, (w.name,)))]
+    xs, ts = [], []
+    for k, ws in enumerate(sources):
+        famc = wfamily(C, ws)
+        n = 8 // len(sources) + (1 if k < 8 % len(sources) else 0)
+        for j in range(ws.count, ws.count + n):
+            p, c = workload.first_accepted(ws, j, lambda p_, c_: C.cr_check_smooth(famc, p_, c_))
+            x, t = C.cr_trace_policy(famc, p, c)
+            xs.append(x)
+            ts.append(t)
     x, t = np.concatenate(xs), np.concatenate(ts)
     m = C.Mlp(seed=2)
     t0 = time.perf_counter()
     losses = m.train(x, t, epochs=8, batch=512, lr=2e-3, seed=4, stream=stream)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    fam = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_LEARNED, mlp=m, launch=fam0.launch)
-    C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+    fam = wfamily(C, w, policy=C.CR_POLICY_LEARNED, mlp=m, launch=fam0.launch)
+    run_batch(C, w, fam, primes, coeffs, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+        res = run_batch(C, w, fam, primes, coeffs, stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     st = res["stats"]
-    famp = C.family(w.nvars, w.degree, w.s_mask, policy=C.CR_POLICY_P_CHUNK, launch=fam0.launch)
-    resp = C.cr_frobenius_batch(famp, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+    famp = wfamily(C, w, policy=C.CR_POLICY_P_CHUNK, launch=fam0.launch)
+    resp = run_batch(C, w, famp, primes, coeffs, stream)
     m.close()
     return {"value": len(primes) / wall, "unit": "frobenius_matrices/s", "ms_per_step": wall * 1e3,
-            "column_steps": st.column_steps, "merged_terms": st.merged_terms, "fallbacks": st.fallbacks,
+            "trained_on": [ws.name for ws in sources], "column_steps": st.column_steps,
+            "merged_terms": st.merged_terms, "fallbacks": st.fallbacks,
             "p_chunk_column_steps": resp["stats"].column_steps, "p_chunk_merged_terms": resp["stats"].merged_terms,
             "reduce_ms": st.reduce_ms, "p_chunk_reduce_ms": resp["stats"].reduce_ms,
             "train_rows": int(x.shape[0]), "train_s": train_s, "train_loss": [float(losses[0]), float(losses[-1])]}
@@ -213,7 +256,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     w = workload.WORKLOADS[args.workload]
-    fam = C.family(w.nvars, w.degree, w.s_mask)
+    fam = wfamily(C, w)
     items = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(fam, p, c)) for j in range(w.count)]
     primes = np.asarray([p for p, _ in items], dtype=np.int32)
     coeffs = np.asarray([c for _, c in items], dtype=np.uint32)
@@ -240,12 +283,12 @@ def main():
         fam.launch = launch_names.index(args.launch)
 
     for _ in range(args.warmup):
-        C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+        run_batch(C, w, fam, primes, coeffs, stream)
     torch.cuda.synchronize()
     tot = {"reduce_ms": 0.0, "combine_ms": 0.0, "psi_ms": 0.0, "assemble_ms": 0.0, "setup_ms": 0.0, "finish_ms": 0.0}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = C.cr_frobenius_batch(fam, primes, coeffs, stream=stream, want_scaled=False, lpoly_ints=False)
+        res = run_batch(C, w, fam, primes, coeffs, stream)
         for k in tot:
             tot[k] += getattr(res["stats"], k)
     torch.cuda.synchronize()
@@ -301,9 +344,15 @@ def main():
                      "avg_launch_ms": tot["reduce_ms"] / args.steps / max(1, st.reduce_launches),
                      "work_per_column_step_int8_ops": work_per_colstep},
     }
+    if w.r:  # precision override: the Frobenius matrices mod p^M, Q(T) out of reach
+        line["config"]["precision"] = {"r": w.r, "n_series": w.n_series,
+                                       "M": {int(p): C.cr_precision(fam, int(p))[2] for p in set(primes.tolist())}}
     if not args.no_legs:
         line["plain"] = plain_leg(C, w, items, args.plain_sample, stream)
         line["learned"] = learned_leg(C, w, fam, items, primes, coeffs, stream, max(1, args.steps // 2))
+        if w.name in TRAIN_FROM:  # the same, with a network trained on other items of this family
+            line["learned_same_family"] = learned_leg(C, w, fam, items, primes, coeffs, stream,
+                                                      max(1, args.steps // 2), train_from=(w.name,))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, items)
     print(json.dumps(line), flush=True)

@@ -323,8 +323,11 @@ cr_status cr_trace_policy(const cr_family *fam, int32_t p, const uint32_t *coeff
  * gather, quad, VALU) x persistent grid (1 or 2 workgroups per CU).  Each
  * configuration runs once to warm up and `trials` times timed (wall clock of
  * whole cr_frobenius_batch calls); configurations whose kernel differs from
- * the one requested (cr_stats.engine) are not counted.  Every configuration
- * gives the same bits.
+ * the one requested (cr_stats.engine) are not counted, nor calls that fail,
+ * except that items reporting CR_EPRECISION after a reduction that ran (an
+ * overridden precision too small to recover Q(T); their Frobenius matrices
+ * are still computed) count as done.  Every configuration gives the same
+ * bits.
  *   ms[policy * 3 + launch]   stage-1 mean times (-1 when not run)
  *   shape_ms[k]               stage-2 mean times for the shapes
  *                             (engine, grid) = (0,1) (0,2) (3,1) (3,2) (2,1) (4,1) (4,2) (1,1)

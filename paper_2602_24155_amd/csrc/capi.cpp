@@ -1754,7 +1754,9 @@ cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes
         }
     }
     // mean wall time of `trials` calls after one warm-up call; -1 if a call
-    // fails, or (for an explicit engine) ran another kernel than the one asked for
+    // fails, or (for an explicit engine) ran another kernel than the one asked
+    // for.  Items whose Q(T) is out of reach of an overridden precision
+    // (CR_EPRECISION after the reduction ran) do not make the call a failure.
     auto time_cfg = [&](const cr_family &f) -> double {
         double tot = 0;
         for (int r = 0; r <= trials; r++) {
@@ -1762,7 +1764,12 @@ cr_status cr_autotune(const cr_family *fam, int32_t count, const int32_t *primes
             auto t0 = std::chrono::steady_clock::now();
             cr_status cs = cr_frobenius_batch(&f, count, primes, coeffs, frob.data(), nullptr, pole.data(),
                                               prec.data(), lp.data(), ist.data(), &st, hip_stream);
-            if (cs != CR_OK || (f.engine != 0 && st.engine != f.engine)) return -1;
+            bool ran = cs == CR_OK;
+            if (!ran && cs == CR_EPRECISION && st.column_steps > 0) {
+                ran = true;
+                for (int i = 0; i < count; i++) ran = ran && (ist[i] == CR_OK || ist[i] == CR_EPRECISION);
+            }
+            if (!ran || (f.engine != 0 && st.engine != f.engine)) return -1;
             if (r > 0) tot += ms_since(t0);
         }
         return tot / trials;

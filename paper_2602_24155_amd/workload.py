@@ -8,6 +8,9 @@ consumer accepts one.  Whether a candidate is smooth is decided by the
 consumer (the library's own validation, or a reference implementation in
 the tests): this module only produces numbers.
 
+A workload may override the precision (r, N_m), for families whose full
+precision exceeds the residues of the device path.
+
 The workloads stand in for the paper's random dense hypersurfaces
 (Tables 1-2 and Section 6); the paper's example files are not used.  The
 sparse workload stands in for the six-term surfaces of Table 2 and the
@@ -32,6 +35,8 @@ class Workload:
     count: int
     s_mask: int = 0  # 0 = all variables (smooth case)
     extra_terms: int = 0  # > 0: Fermat plus this many random monomials (sparse); 0: dense
+    r: int = 0  # relative precision override (0: the precision rule of Section 2.5)
+    n_series: int = 0  # series terms N_m override (0: the rule)
 
     @property
     def ncoeff(self):
@@ -45,6 +50,10 @@ WORKLOADS = {
     "quintic_curves_p31": Workload(6, "quintic_curves_p31", 3, 5, (31,), 256),
     "quartic_k3_mixed": Workload(3, "quartic_k3_mixed", 4, 4, (7, 11, 13), 64),
     "quintic_surfaces_mixed": Workload(4, "quintic_surfaces_mixed", 4, 5, (7, 11), 16),
+    # the same 16 quintic surfaces (same streams) at relative precision 8 with
+    # two series terms: p^M = 7^9, 11^9 fit one 64-bit word, where the full
+    # precision (p^M up to 2^135) does not
+    "quintic_surfaces_r8": Workload(4, "quintic_surfaces_r8", 4, 5, (7, 11), 16, r=8, n_series=2),
     "cubic_fourfold_f7": Workload(5, "cubic_fourfold_f7", 6, 3, (7,), 1, s_mask=1 << 5),
     "sparse_k3_mixed": Workload(7, "sparse_k3_mixed", 4, 4, (7, 11, 13), 64, extra_terms=2),
     "cubic_threefold_f7": Workload(8, "cubic_threefold_f7", 5, 3, (7,), 1, s_mask=1 << 4),

@@ -54,6 +54,13 @@ def test_golden_trace_matches_point_count_mod_p2():
         assert (1 + p + p * p + tr - count_projective(f, 4, p, 1)) % (p * p) == 0
 
 
+def test_reduced_precision_workload_shares_the_items():
+    a, b = workload.WORKLOADS["quintic_surfaces_mixed"], workload.WORKLOADS["quintic_surfaces_r8"]
+    assert (a.wid, a.nvars, a.degree, a.primes, a.count) == (b.wid, b.nvars, b.degree, b.primes, b.count)
+    assert (b.r, b.n_series) == (8, 2) and (a.r, a.n_series) == (0, 0)
+    assert [workload.stream(b, j)[0] for j in range(16)] == [workload.stream(a, j)[0] for j in range(16)]
+
+
 def test_library_precision_for_the_overrides():
     for it in golden():
         fam = C.family(4, 5, r=it["r"], n_series=it["N"])
@@ -80,3 +87,40 @@ def test_gpu_refuses_full_precision():
     it = golden()[0]
     res = C.cr_frobenius_batch(C.family(4, 5), [it["p"]], [it["coeffs"]], raise_on_error=False)
     assert res["item_status"][0] == C.CR_EPRECISION
+
+
+@pytest.mark.gpu
+def test_gpu_learned_policy_on_quintic_surfaces_keeps_the_bits():
+    """A network trained on the GPU only from the plain p-chunk traces of
+    plane quartics, plane quintics and quartic K3 surfaces (no quintic
+    surface among them) plans the reductions of the stored quintic surfaces
+    at reduced precision: the judge keeps or replaces each plan, and the
+    matrices equal the oracle's bit for bit.  The column steps of the learned
+    and the p-chunk plans are printed side by side."""
+    from tests.gpu_common import workload_items
+    xs, ts = [], []
+    for nv, d, name, js in [(3, 4, "quartic_curve_f7", [1, 2]), (3, 5, "quintic_curves_mixed", range(300, 303)),
+                            (4, 4, "quartic_k3_mixed", [70, 71])]:
+        for p, c in workload_items(name, js):
+            x, t = C.cr_trace_policy(C.family(nv, d), p, c)
+            xs.append(x)
+            ts.append(t)
+    m = C.Mlp(seed=5)
+    losses = m.train(np.concatenate(xs), np.concatenate(ts), epochs=6, batch=1024, lr=2e-3, seed=3)
+    assert losses[-1] < losses[0]
+    items = golden()
+    primes, coeffs = [it["p"] for it in items], [it["coeffs"] for it in items]
+    res = C.cr_frobenius_batch(C.family(4, 5, r=8, n_series=2, policy=C.CR_POLICY_LEARNED, mlp=m), primes, coeffs,
+                               raise_on_error=False)
+    st = res["stats"]
+    assert st.policy == C.CR_POLICY_LEARNED and 0 <= st.fallbacks <= len(items)
+    pc = sum(C.cr_policy_cost(C.family(4, 5, r=8, n_series=2, policy=C.CR_POLICY_P_CHUNK), p, c).column_steps
+             for p, c in zip(primes, coeffs))
+    print("quintic surfaces, column steps: learned %d, p-chunk %d (fallbacks %d of %d)"
+          % (st.column_steps, pc, st.fallbacks, len(items)), flush=True)
+    for i, it in enumerate(items):
+        assert [[int(x) for x in row] for row in res["scaled"][i]] == [[int(x) for x in row] for row in it["scaled"]]
+        prec = it["col_prec"]
+        want = [[int(x) % it["p"] ** prec[c] for c, x in enumerate(row)] for row in it["phi_prime"]]
+        assert [[int(x) for x in row] for row in res["frob"][i]] == want
+    m.close()
