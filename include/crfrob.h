@@ -46,7 +46,7 @@ typedef enum {
     CR_OK = 0,
     CR_EINVAL = 1,        /* bad sizes / null pointers / unsupported nvars, degree, or a family
                              with no device path (a right inverse beyond 2^20 entries and no
-                             MFMA kernel: cubic threefolds and fourfolds) */
+                             MFMA kernel: cubic fourfolds) */
     CR_ENOTPRIME = 2,     /* p is not prime */
     CR_EPRANGE = 3,       /* need 7 <= p < 50, p > n, p not dividing d */
     CR_ESINGULAR = 4,     /* f mod p is singular (Jacobian criterion) */
@@ -99,17 +99,19 @@ typedef struct {
                          items whose digit count allows it (5 or 8 digits for plane quintics),
                          the same kernel with one tile per workgroup for the other items of the
                          batch (10 digits), for four-variable families with S = all (quartic K3
-                         surfaces) the quad kernel, for cubic threefolds with S = {x_4} the
-                         threefold kernel, else the 64-bit VALU kernel), 1 = 64-bit VALU
+                         surfaces) the quad kernel, for cubic threefolds with S = {x_4} and
+                         quintic surfaces the streaming kernel, else the 64-bit VALU
+                         kernel), 1 = 64-bit VALU
                          kernel, 2 = int8-digit MFMA kernel with the gather through LDS, 3 =
                          register-gather MFMA kernel with one tile per workgroup, 4 = quad
                          kernel: int8-digit MFMA for four variables, psi digits streamed from
                          memory row tile by row tile, the gather on the accumulators (each
                          output's source rows in one lane's aligned quad of rows), 5 =
-                         threefold kernel: the same for five variables and S = {x_4} (57
-                         row tiles, 32 K-blocks; the vectors' digit planes in global memory,
-                         each output's five source rows in one lane), always in its
-                         persistent form */
+                         streaming kernel: the same for cubic threefolds with S = {x_4} (57
+                         row tiles, 32 K-blocks, each output's five source rows in one
+                         lane) and quintic surfaces (28 row tiles, 18 K-blocks, the quad
+                         placement), the vectors' digit planes in global memory, always
+                         in its persistent form */
     int32_t launch;   /* reduction launches (int8-digit register-gather and quad kernels; the
                          others always use mode 0): 0 = one workgroup per tile of 32 vectors; 1 = persistent:
                          one grid sized to the device's resident capacity drains the tiles
@@ -145,7 +147,8 @@ typedef struct {
     double finish_ms;        /* host unscaling and L-polynomial recovery */
     int32_t engine;          /* kernel that ran: 0 / 3 / 2 = int8-digit MFMA (register gather with tile
                                 pairs for some or all items / with one tile / LDS gather), 4 = int8-digit MFMA quad kernel
-                                (four variables), 5 = int8-digit MFMA threefold kernel, 1 = 64-bit VALU */
+                                (four variables), 5 = int8-digit MFMA streaming kernel (cubic threefolds,
+                                quintic surfaces), 1 = 64-bit VALU */
     int32_t policy;          /* policy whose plan ran */
     int32_t phases;          /* reduction phases (combine points + 1) of the longest plan */
     int32_t fallbacks;       /* CR_POLICY_LEARNED: items whose learned plan cost more than a

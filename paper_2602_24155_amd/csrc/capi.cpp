@@ -210,9 +210,13 @@ FamilyEntry *get_family(const cr_family *fam, std::string &err) {
         if (ss.empty()) ss.assign(16, -1);
         e->off_slot_src = put(ss.data(), ss.size() * 2);
         int qrt = 0, qrtf = 0, qkb = 0;
-        // the quad placement (quartic K3 surfaces) or the quint placement (cubic threefolds)
-        e->ql_ok = quad_shape(shape, qrt, qrtf, qkb) ? quad_layout(F, qrt, qrtf, e->ql)
-                                                      : wide_shape(shape, qrt, qrtf, qkb) && wide_layout(F, qrt, qrtf, e->ql);
+        // the quad placement (quartic K3 surfaces; quintic surfaces in the streaming
+        // kernel) or the quint placement (cubic threefolds)
+        if (quad_shape(shape, qrt, qrtf, qkb))
+            e->ql_ok = quad_layout(F, qrt, qrtf, e->ql);
+        else
+            e->ql_ok = wide_shape(shape, qrt, qrtf, qkb) &&
+                       (F.nv == 4 ? quad_layout(F, qrt, qrtf, e->ql) : wide_layout(F, qrt, qrtf, e->ql));
         if (!e->ql_ok) e->ql.slot.assign(16, 0);
         e->off_qslots = put(e->ql.slot.data(), e->ql.slot.size() * 4);
         std::vector<int16_t> qs(e->ql.slot_src.begin(), e->ql.slot_src.end());

@@ -1,6 +1,9 @@
-// Exact int8-digit MFMA reduction for cubic threefolds (five variables,
-// degree 3, S = {x_4}: s = 495 outputs, J_S from 1815 source to 1001 target
-// rows; Definition 3.1 and Proposition 3.3 with S a proper subset).
+// Exact int8-digit MFMA reduction for families whose right inverse and
+// digit planes do not stay on chip: cubic threefolds (five variables, degree
+// 3, S = {x_4}: s = 495 outputs, J_S from 1815 source to 1001 target rows;
+// Definition 3.1 and Proposition 3.3 with S a proper subset) and quintic
+// surfaces (four variables, degree 5, S = all: s = 455, J_S from 880 source
+// to 560 target rows).
 //
 // The step is the one of the quad kernel (kernels_quad.hip): for 32 vectors
 // of one hypersurface
@@ -8,23 +11,27 @@
 //   w'[r] = sum_i (u_i + r_i + [i not in S]) t[src(r, i)]   (s values)
 // with t one integer product on the matrix cores over balanced base-B digits
 // (B = p^e <= 169, Q' = B^D) and the gather on the accumulators.  What
-// differs is the size: 57 row tiles of psi and 32 K-blocks, so neither psi's
-// digits nor the vectors' digit planes (D x 32 x 1040 bytes per set, twice
-// the LDS) stay on chip.  Each workgroup keeps its two plane sets in a slice
+// differs is the size: 57 row tiles of psi and 32 K-blocks for threefolds, 28
+// and 18 for quintic surfaces, so neither psi's digits nor the vectors' digit
+// planes (D x 32 x (32 K + 16) bytes per set, more than the LDS holds for
+// two sets) stay on chip.  Each workgroup keeps its two plane sets in a slice
 // of global memory (L2-resident; only the family tables are in LDS) and every
 // wave takes its row tiles two at a time, streaming psi's digit fragments of
 // both and the planes' fragments once for the two, one K-block ahead.  All
-// waves of a workgroup run on one CU,
-// so the workgroup barrier orders their writes and reads of the planes as it
-// does for LDS.
+// waves of a workgroup run on one CU, so the workgroup barrier orders their
+// writes and reads of the planes as it does for LDS.
 //
-// Row placement ("quint" tiles): an output with r_4 >= 1 has five source
-// rows, one per variable; one with r_4 = 0 has only the row of x_4.  The host
-// places, in each lane half's 16 accumulator rows of the first row tiles,
-// three five-source outputs (slots 5 q + i, variable i) and one one-source
-// output (slot 15); the last row tiles hold sixteen one-source outputs per
-// lane half.  330 five-source and 165 one-source outputs fill 55 + 2 row
-// tiles (1815 of 1824 rows).
+// Row placement.  Threefolds ("quint" tiles): an output with r_4 >= 1 has
+// five source rows, one per variable; one with r_4 = 0 has only the row of
+// x_4.  The host places, in each lane half's 16 accumulator rows of the first
+// row tiles, three five-source outputs (slots 5 q + i, variable i) and one
+// one-source output (slot 15); the last row tiles hold sixteen one-source
+// outputs per lane half.  330 five-source and 165 one-source outputs fill 55
+// + 2 row tiles (1815 of 1824 rows).  Quintic surfaces (the quad placement of
+// the K3 kernel): an output with every r_i >= 1 has four source rows, one
+// with a single r_z = 0 only the row of x_z; 165 four-source outputs fill 21
+// quad row tiles (four per lane half, slots 4 q + i), the 4 x 55 one-source
+// outputs 7 more (slot 4 q + t of variable t): 880 of 896 rows.
 //
 // The carry step is the quad kernel's: t = z_k + carry, carry = round(t / B)
 // in fp64 (|t| < 2^48, checked on the host), digit = t - B carry.
@@ -44,8 +51,7 @@ typedef const __attribute__((address_space(1))) v4i gv4i;
 
 constexpr int kWV = 32;       // vectors per tile
 constexpr int kWWaves = 4;    // waves per workgroup
-constexpr int kWNV = 5;       // variables
-constexpr int kWTab = 18432;  // colmap entries (ndir x s) held in LDS
+constexpr int kWTab = 25600;  // colmap entries (ndir x s) held in LDS
 constexpr int kWSmall = 256;  // bytes for the direction and final-exponent tables
 
 template <int NRT, int NKB, int D>
@@ -60,18 +66,19 @@ struct WideShape {
 // u_i != 0, then one unit at a time, round robin over all variables, while
 // v_i < u_i; k = the largest chunk with u - k v >= 0, capped by the pole
 // orders left; dir = index of v in the direction table (-1 if none).
+template <int NV>
 __device__ __forceinline__ void choose_chunk_w(int d, uint32_t smask, int ndir, const int8_t *dirsL, const int *U,
                                                int poles_left, int *v, int &dir, int &k) {
     int left = d;
 #pragma unroll
-    for (int i = 0; i < kWNV; i++) {
+    for (int i = 0; i < NV; i++) {
         v[i] = (left > 0 && ((smask >> i) & 1u) && U[i] != 0) ? 1 : 0;
         left -= v[i];
     }
     for (int guard = 0; guard < 64 && left > 0; guard++) {
         bool moved = false;
 #pragma unroll
-        for (int m = 0; m < kWNV; m++)
+        for (int m = 0; m < NV; m++)
             if (left > 0 && v[m] < U[m]) {
                 v[m]++;
                 left--;
@@ -81,14 +88,14 @@ __device__ __forceinline__ void choose_chunk_w(int d, uint32_t smask, int ndir, 
     }
     k = poles_left;
 #pragma unroll
-    for (int i = 0; i < kWNV; i++)
+    for (int i = 0; i < NV; i++)
         if (v[i]) k = min(k, U[i] / v[i]);
     dir = -1;
     if (left == 0)
         for (int t = 0; t < ndir && dir < 0; t++) {
             bool eq = true;
 #pragma unroll
-            for (int i = 0; i < kWNV; i++) eq = eq && dirsL[kWNV * t + i] == v[i];
+            for (int i = 0; i < NV; i++) eq = eq && dirsL[NV * t + i] == v[i];
             if (eq) dir = t;
         }
 }
@@ -210,42 +217,48 @@ __device__ __forceinline__ void pair_products(const int8_t *abase, const int8_t 
     }
 }
 
-// The outputs of row tile rt held by this lane half: in a quint tile three
-// five-source outputs (slots 5 qd + i, variable i) and one one-source output
-// (slot 15), past the quint tiles sixteen one-source outputs.
-template <int NRTQ, int D, int XS>
+// The outputs of row tile rt held by this lane half.  Five variables (quint
+// tiles): three five-source outputs (slots 5 qd + i, variable i) and one
+// one-source output (slot 15), past the quint tiles sixteen one-source
+// outputs.  Four variables (quad tiles): four four-source outputs (slots
+// 4 qd + i, variable i), past the quad tiles sixteen one-source outputs
+// (slot 4 qd + t of variable t).  NRTQ: the number of quint or quad tiles.
+template <int NV, int NRTQ, int D, int XS>
 __device__ __forceinline__ void finish_rt(int rt, int half, const v16i (&acc)[D], const uint32_t *slotL,
-                                          const int (&up)[kWNV], bool more, const int16_t *cm, int8_t *Xn_c, int vout,
+                                          const int (&up)[NV], bool more, const int16_t *cm, int8_t *Xn_c, int vout,
                                           int fin_row, const int16_t *__restrict__ finmap, uint64_t *hrow,
                                           uint64_t *__restrict__ store, int s, double Bd, double invB, int64_t Bi,
                                           int64_t q, double invq, int &bad) {
+    constexpr int NG = NV == 5 ? 3 : 4;  // multi-source outputs per lane half of a quint / quad tile
     const uint32_t *sb = slotL + (rt * 2 + half) * 16;
     if (rt < NRTQ) {
 #pragma unroll
-        for (int qd = 0; qd < 3; qd++) {
-            const uint32_t w0 = sb[5 * qd];
+        for (int qd = 0; qd < NG; qd++) {
+            const uint32_t w0 = sb[NV * qd];
             const int r = (int)(w0 >> 16);
             if (r == 0xFFFF) continue;
             double z[D];
 #pragma unroll
             for (int k = 0; k < D; k++) z[k] = 0.0;
 #pragma unroll
-            for (int t = 0; t < kWNV; t++) {
-                const double wt = (double)(up[t] + (int)((sb[5 * qd + t] >> 5) & 2047u));
+            for (int t = 0; t < NV; t++) {
+                const double wt = (double)(up[t] + (int)((sb[NV * qd + t] >> 5) & 2047u));
 #pragma unroll
-                for (int k = 0; k < D; k++) z[k] = fma(wt, (double)acc[k][5 * qd + t], z[k]);
+                for (int k = 0; k < D; k++) z[k] = fma(wt, (double)acc[k][NV * qd + t], z[k]);
             }
             emit_w<D, XS>(z, r, more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi, q, invq, bad);
         }
-        const uint32_t w = sb[15];
-        if (w & 1u) {
-            const int iv = (int)((w >> 2) & 7u);
-            const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
-            double z[D];
+        if constexpr (NV == 5) {
+            const uint32_t w = sb[15];
+            if (w & 1u) {
+                const int iv = (int)((w >> 2) & 7u);
+                const double wt = (double)(up[iv] + (int)((w >> 5) & 2047u));
+                double z[D];
 #pragma unroll
-            for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][15];
-            emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi, q,
-                          invq, bad);
+                for (int k = 0; k < D; k++) z[k] = wt * (double)acc[k][15];
+                emit_w<D, XS>(z, (int)(w >> 16), more, cm, Xn_c, vout, fin_row, finmap, hrow, store, s, Bd, invB, Bi,
+                              q, invq, bad);
+            }
         }
     } else {
 #pragma unroll
@@ -265,7 +278,7 @@ __device__ __forceinline__ void finish_rt(int rt, int half, const v16i (&acc)[D]
 
 // One tile (up to 32 vectors of one item) on the workgroup's plane sets X
 // (global memory, 2 XB bytes).
-template <int NRT, int NRTQ, int NKB, int D>
+template <int NV, int NRT, int NRTQ, int NKB, int D>
 __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDigitItem *__restrict__ items,
                           const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
                           const int32_t *__restrict__ cpole, const DevVec *__restrict__ vx,
@@ -293,13 +306,13 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
     const int64_t Bi = it.B, q = (int64_t)it.q;
     const double invq = 1.0 / (double)it.q;
 
-    int U[kWNV] = {0, 0, 0, 0, 0}, V[kWNV] = {0, 0, 0, 0, 0};
+    int U[NV] = {}, V[NV] = {};
     int dir = 0, kleft = 0, pole = fam.n, pend = fam.n, vout = -1;
     if (c < nch) {
         const int g = tile.chain0 + c;
         const DevVec xv = vx[g];
 #pragma unroll
-        for (int i = 0; i < kWNV; i++) U[i] = cu[(size_t)g * kWNV + i];
+        for (int i = 0; i < NV; i++) U[i] = cu[(size_t)g * NV + i];
         pole = cpole[g];
         pend = xv.pend;
         vout = xv.out;
@@ -308,9 +321,9 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
             d0 = xv.dir;
             k0 = pole - pend;
 #pragma unroll
-            for (int i = 0; i < kWNV; i++) V[i] = dirsL[d0 * kWNV + i];
+            for (int i = 0; i < NV; i++) V[i] = dirsL[d0 * NV + i];
         } else {
-            choose_chunk_w(fam.d, fam.smask, fam.ndir, dirsL, U, pole - pend, V, d0, k0);
+            choose_chunk_w<NV>(fam.d, fam.smask, fam.ndir, dirsL, U, pole - pend, V, d0, k0);
         }
         if (d0 < 0 || k0 < 1) {
             bad |= 1;
@@ -346,16 +359,16 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
         const int8_t *Xc = X + cur * XB;
         int8_t *Xn = X + (cur ^ 1) * XB;
         const bool act = pole > pend;
-        int up[kWNV], Vn[kWNV], dirn = dir, kleftn = kleft - 1;
+        int up[NV], Vn[NV], dirn = dir, kleftn = kleft - 1;
 #pragma unroll
-        for (int i = 0; i < kWNV; i++) {
+        for (int i = 0; i < NV; i++) {
             up[i] = U[i] - (act ? V[i] : 0);
             Vn[i] = V[i];
         }
         const bool more = act && pole - 1 > pend;
         if (more && kleftn == 0) {
             int d0, k0;
-            choose_chunk_w(fam.d, fam.smask, fam.ndir, dirsL, up, pole - 1 - pend, Vn, d0, k0);
+            choose_chunk_w<NV>(fam.d, fam.smask, fam.ndir, dirsL, up, pole - 1 - pend, Vn, d0, k0);
             if (d0 < 0 || k0 < 1) {
                 bad |= 1;
                 d0 = 0;
@@ -370,7 +383,7 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
             for (int a = 0; a < fam.nfinU && Ui < 0; a++) {
                 bool eq = true;
 #pragma unroll
-                for (int i = 0; i < kWNV; i++) eq = eq && finUL[kWNV * a + i] == up[i];
+                for (int i = 0; i < NV; i++) eq = eq && finUL[NV * a + i] == up[i];
                 if (eq) Ui = a;
             }
             if (Ui < 0) bad |= 4;
@@ -394,17 +407,17 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
             else
                 pair_products<D, NKB, XS, false>(abase, xbase, rt, rt, acc, acc2);
             if (!act) continue;
-            finish_rt<NRTQ, D, XS>(rt, half, acc, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s,
+            finish_rt<NV, NRTQ, D, XS>(rt, half, acc, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow, store, s,
                                    Bd, invB, Bi, q, invq, bad);
             if (rt2 < NRT)
-                finish_rt<NRTQ, D, XS>(rt2, half, acc2, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow,
+                finish_rt<NV, NRTQ, D, XS>(rt2, half, acc2, slotL, up, more, cm, Xn_c, vout, fin_row, fam.finmap, hrow,
                                        store, s, Bd, invB, Bi, q, invq, bad);
         }
         __syncthreads();  // every wave has read the current planes and written the next ones
         int8_t *Xz = X + cur * XB;
         for (int idx = tid; idx < XB / 16; idx += NT) reinterpret_cast<v4i *>(Xz)[idx] = v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < kWNV; i++) {
+        for (int i = 0; i < NV; i++) {
             U[i] = up[i];
             V[i] = Vn[i];
         }
@@ -421,7 +434,7 @@ __device__ void wide_tile(const DevFamily &fam, const DevTile &tile, const DevDi
 // A persistent grid draining the tile list through the counter *queue (zero
 // at launch; every workgroup leaves once the counter passes ntiles).
 // Workgroup b works on the plane sets at xscratch + 2 XB b.
-template <int NRT, int NRTQ, int NKB, int D>
+template <int NV, int NRT, int NRTQ, int NKB, int D>
 __global__ __launch_bounds__(64 * kWWaves) void k_reduce_wide(
     DevFamily fam, const DevDigitItem *__restrict__ items, const DevTile *__restrict__ tiles, int ntiles,
     int *__restrict__ queue, const int16_t *__restrict__ cu, const int32_t *__restrict__ cg,
@@ -437,8 +450,8 @@ __global__ __launch_bounds__(64 * kWWaves) void k_reduce_wide(
     __shared__ int next;
     const int NT = 64 * kWWaves, tid = threadIdx.x;
     for (int idx = tid; idx < fam.ndir * fam.s; idx += NT) colmapL[idx] = fam.colmap[idx];
-    for (int idx = tid; idx < fam.ndir * kWNV; idx += NT) dirsL[idx] = fam.dirs[idx];
-    for (int idx = tid; idx < fam.nfinU * kWNV; idx += NT) finUL[idx] = fam.finU[idx];
+    for (int idx = tid; idx < fam.ndir * NV; idx += NT) dirsL[idx] = fam.dirs[idx];
+    for (int idx = tid; idx < fam.nfinU * NV; idx += NT) finUL[idx] = fam.finU[idx];
     for (int idx = tid; idx < NRT * 2 * 16; idx += NT) slotL[idx] = slots[idx];
     int8_t *X = xscratch + (size_t)blockIdx.x * 2 * Sh::XB;
     int bad = 0;
@@ -448,36 +461,47 @@ __global__ __launch_bounds__(64 * kWWaves) void k_reduce_wide(
         const int ti = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();  // every thread has read `next` before it is overwritten
         if (ti >= ntiles) break;
-        wide_tile<NRT, NRTQ, NKB, D>(fam, tiles[ti], items, cu, cg, cpole, vx, store, hbuf, bad, X, colmapL, dirsL,
+        wide_tile<NV, NRT, NRTQ, NKB, D>(fam, tiles[ti], items, cu, cg, cpole, vx, store, hbuf, bad, X, colmapL, dirsL,
                                      finUL, slotL);
     }
     if (bad) atomicOr(err, bad);
 }
 
-template <int D>
+template <int NV, int NRT, int NRTQ, int NKB, int D>
 hipError_t launch_wide_one(const DevFamily &fam, const DevDigitItem *items, const DevTile *tiles, int ntiles,
                            const int16_t *cu, const int32_t *cg, const int32_t *cpole, const DevVec *vx,
                            uint64_t *store, uint64_t *hbuf, const uint32_t *slots, int8_t *xscratch, int grid,
                            int *err, int *queue, hipStream_t stream) {
-    constexpr size_t lds = WideShape<57, 32, D>::lds;
-    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_wide<57, 55, 32, D>,
+    constexpr size_t lds = WideShape<NRT, NKB, D>::lds;
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_wide<NV, NRT, NRTQ, NKB, D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reduce_wide<57, 55, 32, D>), dim3(grid), dim3(64 * kWWaves), lds, stream, fam, items, tiles,
-                       ntiles, queue, cu, cg, cpole, vx, store, hbuf, slots, xscratch, err);
+    hipLaunchKernelGGL((k_reduce_wide<NV, NRT, NRTQ, NKB, D>), dim3(grid), dim3(64 * kWWaves), lds, stream, fam,
+                       items, tiles, ntiles, queue, cu, cg, cpole, vx, store, hbuf, slots, xscratch, err);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Shape of the threefold kernel for a family: 57 row tiles (the first 55 of
-// them quint tiles), 32 K-blocks.
+// Shape of the streaming kernel for a family: cubic threefolds (five
+// variables, S = {x_4}): 57 row tiles, the first 55 quint tiles, 32
+// K-blocks; quintic surfaces (four variables, S = all): 28 row tiles, the
+// first 21 quad tiles, 18 K-blocks.
 bool wide_shape(const DevFamily &fam, int &nrt, int &nrtq, int &nkb) {
-    nrt = 57;
-    nrtq = 55;
-    nkb = 32;
-    return fam.nv == kWNV && fam.smask == 0x10u && fam.s == 495 && fam.T == 1001 && fam.nsrc == 1815 &&
-           fam.ndir * fam.s <= kWTab && fam.ndir * kWNV <= kWSmall && fam.nfinU * kWNV <= kWSmall;
+    const bool tables = fam.ndir * fam.s <= kWTab && fam.ndir * fam.nv <= kWSmall && fam.nfinU * fam.nv <= kWSmall;
+    if (fam.nv == 5 && fam.smask == 0x10u && fam.s == 495 && fam.T == 1001 && fam.nsrc == 1815) {
+        nrt = 57;
+        nrtq = 55;
+        nkb = 32;
+        return tables;
+    }
+    if (fam.nv == 4 && fam.smask == 0xFu && fam.s == 455 && fam.T == 560 && fam.nsrc == 880) {
+        nrt = 28;
+        nrtq = 21;
+        nkb = 18;
+        return tables;
+    }
+    return false;
 }
 
 bool wide_supports_digits(int D) { return D >= 4 && D <= 7; }
@@ -502,20 +526,24 @@ hipError_t launch_reduce_wide(const DevFamily &fam, const DevDigitItem *items, c
     if (ntiles == 0) return hipSuccess;
     int nrt, nrtq, nkb;
     if (!wide_shape(fam, nrt, nrtq, nkb) || !wide_supports_digits(D) || !queue) return hipErrorInvalidValue;
-    switch (D) {
-        case 4:
-            return launch_wide_one<4>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, xscratch, grid,
-                                      err, queue, stream);
-        case 5:
-            return launch_wide_one<5>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, xscratch, grid,
-                                      err, queue, stream);
-        case 6:
-            return launch_wide_one<6>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, xscratch, grid,
-                                      err, queue, stream);
-        default:
-            return launch_wide_one<7>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots, xscratch, grid,
-                                      err, queue, stream);
+#define CRF_WIDE(NV, R, RQ, KB, DD)                                                                              \
+    return launch_wide_one<NV, R, RQ, KB, DD>(fam, items, tiles, ntiles, cu, cg, cpole, vx, store, hbuf, slots,       \
+                                              xscratch, grid, err, queue, stream)
+    if (nrt == 57) {
+        switch (D) {
+            case 4: CRF_WIDE(5, 57, 55, 32, 4);
+            case 5: CRF_WIDE(5, 57, 55, 32, 5);
+            case 6: CRF_WIDE(5, 57, 55, 32, 6);
+            default: CRF_WIDE(5, 57, 55, 32, 7);
+        }
     }
+    switch (D) {
+        case 4: CRF_WIDE(4, 28, 21, 18, 4);
+        case 5: CRF_WIDE(4, 28, 21, 18, 5);
+        case 6: CRF_WIDE(4, 28, 21, 18, 6);
+        default: CRF_WIDE(4, 28, 21, 18, 7);
+    }
+#undef CRF_WIDE
 }
 
 }  // namespace crf

@@ -10,7 +10,8 @@ tests/golden/make_quintic_surface_golden.py, which calls only oracle/.
 On the CPU the stored matrices are pinned by brute-force point counts: the
 trace of Frobenius on the primitive H^2, 1 + p + p^2 + tr(Phi) = #X(F_p)
 (Section 1.1), holds modulo p^2 at this precision.  On the GPU the library
-must reproduce the stored matrices bit for bit.
+must reproduce the stored matrices bit for bit, on the streaming MFMA kernel
+and on the 64-bit VALU kernel.
 """
 import json
 import os
@@ -68,11 +69,16 @@ def test_library_precision_for_the_overrides():
 
 
 @pytest.mark.gpu
-def test_gpu_matches_golden_at_reduced_precision():
+@pytest.mark.parametrize("engine,policy", [(C.ENGINE_AUTO, C.CR_POLICY_DEPTH_FIRST), (C.ENGINE_AUTO, C.CR_POLICY_P_CHUNK),
+                                           (C.ENGINE_VALU, C.CR_POLICY_DEPTH_FIRST)])
+def test_gpu_matches_golden_at_reduced_precision(engine, policy):
+    """The streaming MFMA kernel (engine 5: 28 quad row tiles x 18 K-blocks,
+    base-49 / base-121 digits) and the 64-bit VALU kernel reproduce the
+    stored matrices bit for bit."""
     items = golden()
-    fam = C.family(4, 5, r=8, n_series=2)
+    fam = C.family(4, 5, r=8, n_series=2, engine=engine, policy=policy)
     res = C.cr_frobenius_batch(fam, [it["p"] for it in items], [it["coeffs"] for it in items], raise_on_error=False)
-    assert res["stats"].engine == C.ENGINE_VALU
+    assert res["stats"].engine == (C.ENGINE_WIDE if engine == C.ENGINE_AUTO else C.ENGINE_VALU)
     for i, it in enumerate(items):
         assert [[int(x) for x in row] for row in res["scaled"][i]] == [[int(x) for x in row] for row in it["scaled"]]
         assert [int(x) for x in res["col_pole"][i]] == it["col_pole"]
