@@ -130,3 +130,27 @@ def test_gpu_learned_policy_on_quintic_surfaces_keeps_the_bits():
         want = [[int(x) % it["p"] ** prec[c] for c, x in enumerate(row)] for row in it["phi_prime"]]
         assert [[int(x) for x in row] for row in res["frob"][i]] == want
     m.close()
+
+
+@pytest.mark.gpu
+def test_gpu_full_reduced_precision_batch():
+    """The whole 16-surface workload at reduced precision: the streaming MFMA
+    kernel and the 64-bit VALU kernel give the same scaled matrices, and on
+    every surface the trace of Frobenius gives #X(F_p) modulo p^2 (brute-force
+    point count)."""
+    w = workload.WORKLOADS["quintic_surfaces_r8"]
+    fam = C.family(4, 5, r=w.r, n_series=w.n_series)
+    items = [workload.first_accepted(w, j, lambda p, c: C.cr_check_smooth(fam, p, c)) for j in range(w.count)]
+    primes, coeffs = [p for p, _ in items], [c for _, c in items]
+    res = C.cr_frobenius_batch(fam, primes, coeffs, raise_on_error=False)
+    assert res["stats"].engine == C.ENGINE_WIDE
+    ref = C.cr_frobenius_batch(C.family(4, 5, r=w.r, n_series=w.n_series, engine=C.ENGINE_VALU), primes, coeffs,
+                               raise_on_error=False)
+    assert ref["stats"].engine == C.ENGINE_VALU
+    assert np.array_equal(res["scaled"], ref["scaled"]) and np.array_equal(res["frob"], ref["frob"])
+    for i, (p, c) in enumerate(items):
+        assert int(res["item_status"][i]) in (C.CR_OK, C.CR_EPRECISION)
+        pole = [int(x) for x in res["col_pole"][i]]
+        tr = sum(int(res["frob"][i][k][k]) * p ** (3 - pole[k]) for k in range(52))
+        f = {e: v % p for e, v in from_coeffs(4, 5, c).items() if v % p}
+        assert (1 + p + p * p + tr - count_projective(f, 4, p, 1)) % (p * p) == 0
