@@ -152,7 +152,7 @@ struct FamilyEntry {
     size_t off_colmap, off_gsrc, off_gw, off_finmap, off_dirs, off_finU, off_slots, off_slot_src, off_qslots, off_qslot_src;
     BinLayout bl;  // source-row placement for the register-gather MFMA kernel
     bool bl_ok = false;
-    BinLayout ql;  // row placement of the quad kernel (or of the threefold kernel)
+    BinLayout ql;  // row placement of the quad kernel (or of the streaming kernel)
     bool ql_ok = false;
 };
 
@@ -503,7 +503,7 @@ struct BatchCtx {
     int nco = 0, sdim = 0, b = 0, nrt = 0, nkb = 0, policy = 0;
     bool want_mfma = false, use_bins = false;
     bool quad = false;        // four-variable int8-digit MFMA kernel (k_reduce_quad)
-    bool wide = false;        // cubic-threefold int8-digit MFMA kernel (k_reduce_wide)
+    bool wide = false;        // streaming int8-digit MFMA kernel (k_reduce_wide: threefolds, quintic surfaces)
     bool psi_global = false;  // device psi with [J | I] in global memory (k_psi_global)
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
@@ -614,7 +614,7 @@ struct SubBatch {
     size_t h_end = 0, o_items = 0, o_tiles = 0, o_ditems = 0, o_tables = 0, o_cu = 0, o_cg = 0, o_cp = 0, o_vx = 0;
     size_t o_comb = 0, o_msrc = 0, o_malpha = 0, o_err = 0, o_Y = 0, o_hbuf = 0, o_store = 0, o_queue = 0;
     size_t o_psi_dev = 0;
-    size_t o_xw = 0;  // threefold kernel: digit planes in global memory
+    size_t o_xw = 0;  // streaming kernel: digit planes in global memory
     DevFamily df{};
     hipEvent_t ep = nullptr, epe = nullptr, e0 = nullptr, em = nullptr, e1 = nullptr, edone = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cev;
@@ -842,7 +842,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     if (sb.use_mfma && dpsi)
         for (int li = 0; li < nlive; li++) apack_off[li] = take(sb.items[sb.live[li]].apack.size());
     sb.o_queue = take(4 * std::max<size_t>(sb.launches.size(), 1));
-    if (sb.use_mfma && ctx.wide) {  // digit planes of the threefold kernel, per workgroup of the persistent grid
+    if (sb.use_mfma && ctx.wide) {  // digit planes of the streaming kernel, per workgroup of the persistent grid
         int dmax = 1;
         for (int li = 0; li < nlive; li++) dmax = std::max(dmax, sb.dps[sb.live[li]].D);
         sb.o_xw = take(wide_scratch_bytes(dmax, wide_grid(1 << 30, std::max(1, ctx.fam->grid))));
@@ -1038,7 +1038,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     uint64_t *storep = reinterpret_cast<uint64_t *>(db + sb.o_store);
     uint64_t *hb64 = reinterpret_cast<uint64_t *>(db + sb.o_hbuf);
     int *errp = reinterpret_cast<int *>(db + sb.o_err);
-    // the threefold kernel always runs its persistent form (its digit planes are per workgroup)
+    // the streaming kernel always runs its persistent form (its digit planes are per workgroup)
     const int mode = sb.use_mfma && ctx.wide ? std::max(1, ctx.fam->launch)
                                              : (sb.use_mfma && (sb.use_bins || ctx.quad) ? ctx.fam->launch : 0);
     const int pgrid = mode > 0 ? std::max(1, ctx.fam->grid) : 0;  // persistent: workgroups per CU

@@ -169,15 +169,16 @@ bool bin_layout(const Family &fam, int nrt, BinLayout &bl);
 // an empty full quad).  False if the family's groups do not fit.
 bool quad_layout(const Family &fam, int nrt, int nrtf, BinLayout &bl);
 
-// Row placement of the cubic-threefold kernel (five variables, S = {x_4}):
+// Row placement of the streaming kernel for cubic threefolds (five variables, S = {x_4}):
 // nrt row tiles, the first nrtq of them "quint" tiles whose lane halves hold
 // three five-source outputs (slots 5 q + i: variable i) and one one-source
 // output (slot 15), the others sixteen one-source outputs per lane half; slot
 // words as in BinLayout (bits 2-4 the variable, r = 0xFFFF marks an empty
 // five-source group).  False if the family's outputs do not fit.
 bool wide_layout(const Family &fam, int nrt, int nrtq, BinLayout &bl);
-// Digits of the quad kernel: B = p^e <= 169, D = ceil(M / e), Q' = B^D < 2^52,
-// int32 position sums, carry sums below 2^48.
+// Digits of the quad and streaming kernels: B = p^e <= 169, D = ceil(M / e),
+// Q' = B^D < 2^52, int32 position sums, carry sums below 2^48; z32 set when
+// the position sums fit 24-bit multiplies and the carry sums int32.
 bool quad_digit_params(int p, int M, int T, int nv, u64 wtmax, DigitParams &dp);
 
 // psi digits in v_mfma_i32_32x32x32_i8 A-fragment order:
