@@ -51,6 +51,9 @@ hipError_t launch_reduce_mfma5(const DevFamily &fam, const DevDigitItem *items, 
                                int pgrid, int *queue, hipStream_t stream);
 size_t psi_lds_bytes(int R, int C);
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream);
+hipError_t launch_psi_multi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, uint64_t *work,
+                            unsigned char *book, hipStream_t stream);
+size_t psi_book_bytes(int R, int C);
 hipError_t launch_psi_global(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, uint64_t *work,
                              hipStream_t stream);
 hipError_t launch_pack_psi(const DevItem *items, const DevDigitItem *ditems, int nitems, const int16_t *slot_src,
@@ -505,6 +508,7 @@ struct BatchCtx {
     bool quad = false;        // four-variable int8-digit MFMA kernel (k_reduce_quad)
     bool wide = false;        // streaming int8-digit MFMA kernel (k_reduce_wide: threefolds, quintic surfaces)
     bool psi_global = false;  // device psi with [J | I] in global memory (k_psi_global)
+    bool psi_multi = false;   // the same elimination spread over the device (k_gj_*)
     bool device_psi = false;  // psi computed by k_psi (its [J | I] fits in LDS)
     bool pairs = false;       // two interleaved tiles per workgroup (k_reduce_mfma5)
     hipStream_t stream = nullptr;
@@ -575,9 +579,13 @@ struct BatchCtx {
             device_psi = true;
             psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
         }
-        if (wide) {  // host psi (its [J | I] is 22 MB), digits packed on the host in the quint placement
+        if (wide) {
+            // threefolds: host psi (its [J | I] is 22 MB per item, and the device-wide
+            // elimination would stream it once per pivot), digits packed on the host in the
+            // quint placement; quintic surfaces: device psi by the device-wide elimination
+            // ([J | I] of 6.5 MB per item), digits packed on the device in the quad placement
             use_bins = pairs = false;
-            device_psi = false;
+            device_psi = psi_multi = F->nv == 4;
         }
         // without an MFMA kernel the 64-bit VALU kernel reads psi[:, cols(v)] from memory
         // for every step of every vector, two vectors per workgroup when psi is large;
@@ -701,7 +709,7 @@ cr_status prepare_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
     // pair kernel takes get their psi digits folded, the others run on single tiles
     sb.use_pairs = sb.use_mfma && sb.use_bins && ctx.pairs && ctx.device_psi;
     auto pairs_for = [&](int D) { return sb.use_pairs && mfma5_supports(df, D); };
-    if (sb.use_mfma && !sb.use_bins && !ctx.quad && ctx.device_psi)
+    if (sb.use_mfma && !sb.use_bins && !ctx.quad && !ctx.wide && ctx.device_psi)
         sb.use_mfma = false;  // device packing follows the bin layout (or the quad placement)
     if (!sb.use_mfma && ctx.device_psi && ctx.want_mfma) {
         // an item the MFMA kernel cannot take: the VALU kernel reads psi from k_psi directly
@@ -1021,7 +1029,7 @@ cr_status launch_sub(BatchCtx &ctx, SubBatch &sb, std::string &msg) {
         if (he == hipSuccess && sb.use_mfma)
             he = launch_pack_psi(dv, reinterpret_cast<const DevDigitItem *>(db + sb.o_ditems), nlive,
                                  reinterpret_cast<const int16_t *>(
-                                     db + sb.o_tables + (ctx.quad ? ctx.fe->off_qslot_src : ctx.fe->off_slot_src)),
+                                     db + sb.o_tables + (ctx.quad || ctx.wide ? ctx.fe->off_qslot_src : ctx.fe->off_slot_src)),
                                  ctx.nrt,
                                  ctx.nkb, ctx.F->tgt.count, ctx.F->nsrc, sb.use_pairs ? 1 : 0, aux);
         (void)hipEventRecord(sb.epe, aux);
@@ -1384,7 +1392,9 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     const size_t h_end = off;
     const size_t o_psi = take(8 * psi_len * count);
     // [J | I] of every item, for the global-memory elimination
-    const size_t o_work = ctx.psi_global ? take(8 * (size_t)F.tgt.count * (F.nsrc + F.tgt.count) * count) : 0;
+    const size_t o_work =
+        ctx.psi_global || ctx.psi_multi ? take(8 * (size_t)F.tgt.count * (F.nsrc + F.tgt.count) * count) : 0;
+    const size_t o_book = ctx.psi_multi ? take(psi_book_bytes(F.tgt.count, F.nsrc) * count) : 0;
     Arena &ar = *ctx.psi_arena;
     if (!ar.ensure(off, h_end)) {
         msg = ar.fixed ? "the right inverses of J_S need " + std::to_string(off) + " bytes of device memory; the "
@@ -1436,7 +1446,11 @@ cr_status start_psi_all(BatchCtx &ctx, int count, std::string &msg) {
     (void)hipEventCreate(&ctx.psi_done);
     if (he == hipSuccess) he = hipMemcpyAsync(db, hb, h_end, hipMemcpyHostToDevice, aux);
     (void)hipEventRecord(ctx.psi_t0, aux);
-    if (he == hipSuccess && ctx.psi_global)
+    if (he == hipSuccess && ctx.psi_multi)
+        he = launch_psi_multi(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
+                              reinterpret_cast<const int32_t *>(db + o_jtab), reinterpret_cast<uint64_t *>(db + o_work),
+                              db + o_book, aux);
+    else if (he == hipSuccess && ctx.psi_global)
         he = launch_psi_global(reinterpret_cast<const DevItem *>(db + o_items), count, F.tgt.count, F.nsrc,
                                reinterpret_cast<const int32_t *>(db + o_jtab),
                                reinterpret_cast<uint64_t *>(db + o_work), aux);

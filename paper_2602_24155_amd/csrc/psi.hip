@@ -74,6 +74,11 @@ size_t psi_lds_bytes(int R, int C) { return (size_t)R * (C + R) * 8 + (size_t)(R
 // LDS of the global-memory form: everything but [J | I]
 size_t psi_small_lds_bytes(int R, int C) { return (size_t)(R + 1) * 8 + (size_t)C * 4 + 32; }
 
+// bytes of one item's bookkeeping in the device-wide elimination (16-byte aligned)
+__host__ __device__ inline size_t gj_book_bytes(int R, int C) {
+    return ((size_t)(R + 1) * 8 + (size_t)(C + 2) * 4 + 15) / 16 * 16;
+}
+
 // J_S is built from the coefficients of f and the family table jtab: entry
 // (r, k) = c_e * w for jtab[r C + k] = (e << 8) | w, or 0 for -1.  `a` holds
 // [J | I] (R x (C + R)), in LDS (k_psi) or in global memory (k_psi_global,
@@ -222,6 +227,150 @@ __global__ __launch_bounds__(256) void k_pack_psi(const DevItem *__restrict__ it
     }
     // unfolded: fragment i holds digit i; folded: fragment i holds digit i - Jf
     for (int i = 0; i < D; i++) out[(size_t)i * nkb * 1024] = !folded ? dig[i] : (inside && Jf <= i ? dig[i - Jf] : 0);
+}
+
+// The same elimination spread over the whole device, for families whose
+// [J | I] is too large for one workgroup to stream once per pivot (quintic
+// surfaces: 560 x 1440 words per item).  Per pivot row r, one launch finds
+// the pivot of every item (one wave each: the first unused column holding a
+// unit mod p, its inverse, the row scaled, the pivot column snapshot), and
+// one launch clears that column from every other row of every item (one wave
+// per row, skipping the rows already zero there).  The pivots, and so psi,
+// are those of the one-workgroup form.  Per-item bookkeeping in `book`:
+// used[C] (pivot row + 1 of each column), fcol[R], then {pivot column,
+// failure} and the pivot inverse.
+constexpr int kGjWaves = 4;
+
+struct GjBook {
+    int *used;
+    uint64_t *fcol;
+    int *state;
+    uint64_t *inv;
+};
+
+__device__ __forceinline__ static GjBook gj_book(unsigned char *book, int item, int R, int C) {
+    unsigned char *b = book + (size_t)item * gj_book_bytes(R, C);
+    GjBook g;
+    g.fcol = reinterpret_cast<uint64_t *>(b);
+    g.inv = g.fcol + R;
+    g.used = reinterpret_cast<int *>(g.inv + 1);
+    g.state = g.used + C;
+    return g;
+}
+
+// [J | I] rows and cleared bookkeeping; grid (row blocks, items)
+__global__ __launch_bounds__(64 * kGjWaves) void k_gj_init(const DevItem *__restrict__ items, int R, int C,
+                                                            const int32_t *__restrict__ jtab, uint64_t *work,
+                                                            unsigned char *book) {
+    const DevItem it = items[blockIdx.y];
+    if (it.q == 0) return;
+    const PMod md{it.q, it.mu, it.sbits};
+    const int W = C + R, lane = threadIdx.x & 63, r = blockIdx.x * kGjWaves + (threadIdx.x >> 6);
+    uint64_t *a = work + (size_t)blockIdx.y * R * W;
+    const GjBook g = gj_book(book, blockIdx.y, R, C);
+    if (r < R)
+        for (int k = lane; k < W; k += 64)
+            if (k < C) {
+                const int32_t e = jtab[(size_t)r * C + k];
+                a[(size_t)r * W + k] = e < 0 ? 0 : md.reduce((u128p)it.fcoef[e >> 8] * (uint32_t)(e & 255));
+            } else {
+                a[(size_t)r * W + k] = (uint64_t)(k - C == r);
+            }
+    for (int k = blockIdx.x * 64 * kGjWaves + threadIdx.x; k < C; k += gridDim.x * 64 * kGjWaves) g.used[k] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.state[0] = g.state[1] = 0;
+}
+
+// pivot of row r of every item: one wave per item
+__global__ __launch_bounds__(64) void k_gj_pivot(const DevItem *__restrict__ items, int R, int C, int r,
+                                                 uint64_t *work, unsigned char *book) {
+    const DevItem it = items[blockIdx.x];
+    if (it.q == 0) return;
+    const GjBook g = gj_book(book, blockIdx.x, R, C);
+    if (g.state[1]) return;  // uniform over the wave
+    const PMod md{it.q, it.mu, it.sbits};
+    const uint32_t p = (uint32_t)it.p, two32p = (uint32_t)((1ull << 32) % p);
+    const int W = C + R, lane = threadIdx.x;
+    uint64_t *a = work + (size_t)blockIdx.x * R * W;
+    uint64_t *row = a + (size_t)r * W;
+    int c = C;
+    for (int k0 = 0; k0 < C && c == C; k0 += 64) {
+        const int k = k0 + lane;
+        const bool ok = k < C && !g.used[k] && mod_small(row[k], p, two32p) != 0;
+        const unsigned long long m = __ballot(ok);
+        if (m) c = k0 + __ffsll((long long)m) - 1;
+    }
+    if (c == C) {  // J_S is not surjective mod p
+        if (lane == 0) {
+            g.state[1] = 1;
+            atomicOr(it.flag, 1);
+        }
+        return;
+    }
+    uint64_t inv = 0;
+    if (lane == 0) inv = inv_mod(md, row[c], p, two32p);
+    inv = __shfl(inv, 0);
+    for (int r2 = lane; r2 < R; r2 += 64) g.fcol[r2] = r2 == r ? 0 : a[(size_t)r2 * W + c];
+    for (int k = lane; k < W; k += 64) row[k] = md.mul(row[k], inv);
+    if (lane == 0) {
+        g.used[c] = r + 1;
+        g.state[0] = c;
+    }
+}
+
+// column c_r cleared from every other row: grid (row blocks, items), one wave per row
+__global__ __launch_bounds__(64 * kGjWaves) void k_gj_update(const DevItem *__restrict__ items, int R, int C, int r,
+                                                              uint64_t *work, unsigned char *book) {
+    const DevItem it = items[blockIdx.y];
+    if (it.q == 0) return;
+    const GjBook g = gj_book(book, blockIdx.y, R, C);
+    if (g.state[1]) return;
+    const int r2 = blockIdx.x * kGjWaves + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r2 >= R) return;
+    const uint64_t f = g.fcol[r2];
+    if (f == 0) return;  // row r itself, and rows already zero in the pivot column
+    const PMod md{it.q, it.mu, it.sbits};
+    const int W = C + R;
+    uint64_t *a = work + (size_t)blockIdx.y * R * W;
+    const uint64_t *row = a + (size_t)r * W;
+    uint64_t *o = a + (size_t)r2 * W;
+    for (int k = lane; k < W; k += 64) {
+        const uint64_t y = row[k];
+        if (y == 0) continue;
+        const uint64_t t = md.mul(f, y);
+        const uint64_t x = o[k];
+        o[k] = x >= t ? x - t : x + md.q - t;
+    }
+}
+
+// psi (C x R): row c = pivot of row r -> right half of row r; grid (column blocks, items)
+__global__ __launch_bounds__(64 * kGjWaves) void k_gj_emit(const DevItem *__restrict__ items, int R, int C,
+                                                            const uint64_t *work, unsigned char *book) {
+    const DevItem it = items[blockIdx.y];
+    if (it.q == 0) return;
+    const GjBook g = gj_book(book, blockIdx.y, R, C);
+    const bool fail = g.state[1] != 0;
+    const int cc = blockIdx.x * kGjWaves + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (cc >= C) return;
+    const int r1 = g.used[cc];
+    const uint64_t *a = work + (size_t)blockIdx.y * R * (C + R);
+    for (int j = lane; j < R; j += 64)
+        it.psi_out[(size_t)cc * R + j] = (!fail && r1 > 0) ? a[(size_t)(r1 - 1) * (C + R) + C + j] : 0;
+}
+
+size_t psi_book_bytes(int R, int C) { return gj_book_bytes(R, C); }
+
+hipError_t launch_psi_multi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, uint64_t *work,
+                            unsigned char *book, hipStream_t stream) {
+    if (nitems == 0) return hipSuccess;
+    const dim3 rows((R + kGjWaves - 1) / kGjWaves, nitems), block(64 * kGjWaves);
+    hipLaunchKernelGGL(k_gj_init, rows, block, 0, stream, items, R, C, jtab, work, book);
+    for (int r = 0; r < R; r++) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(nitems), dim3(64), 0, stream, items, R, C, r, work, book);
+        hipLaunchKernelGGL(k_gj_update, rows, block, 0, stream, items, R, C, r, work, book);
+    }
+    hipLaunchKernelGGL(k_gj_emit, dim3((C + kGjWaves - 1) / kGjWaves, nitems), block, 0, stream, items, R, C,
+                       (const uint64_t *)work, book);
+    return hipGetLastError();
 }
 
 hipError_t launch_psi(const DevItem *items, int nitems, int R, int C, const int32_t *jtab, hipStream_t stream) {
