@@ -580,12 +580,11 @@ struct BatchCtx {
             psi_global = psi_lds_bytes(F->tgt.count, F->nsrc) > 150 * 1024;
         }
         if (wide) {
-            // threefolds: host psi (its [J | I] is 22 MB per item, and the device-wide
-            // elimination would stream it once per pivot), digits packed on the host in the
-            // quint placement; quintic surfaces: device psi by the device-wide elimination
-            // ([J | I] of 6.5 MB per item), digits packed on the device in the quad placement
+            // device psi by the device-wide elimination ([J | I] of 6.5 MB per quintic
+            // surface, 22 MB per cubic threefold), digits packed on the device in the quad
+            // or quint placement
             use_bins = pairs = false;
-            device_psi = psi_multi = F->nv == 4;
+            device_psi = psi_multi = true;
         }
         // without an MFMA kernel the 64-bit VALU kernel reads psi[:, cols(v)] from memory
         // for every step of every vector, two vectors per workgroup when psi is large;
@@ -1201,8 +1200,11 @@ cr_status complete_sub(BatchCtx &ctx, SubBatch &sb, std::vector<cr_status> &st, 
         const int i = sb.live[li], g = sb.idx[i];
         const size_t bb = (size_t)b * b;
         if (flags[li] || (ctx.psi_flags && ctx.psi_flags[g])) {
-            st[g] = CR_ESINGULAR;
-            errs[g] = "J_S is not surjective mod p (no unit pivot)";
+            // J_S not surjective mod p: f is singular (S = all) or not S-smooth (Definition 3.1)
+            const bool all = ctx.F->nS == ctx.F->nv;
+            st[g] = all ? CR_ESINGULAR : CR_ENOT_S_SMOOTH;
+            errs[g] = all ? "J_S is not surjective mod p (no unit pivot): f is singular mod p"
+                          : "J_S is not surjective mod p (no unit pivot): f is not S-smooth";
             return;
         }
         st[g] = finish_item(*ctx.F, sb.items[i], Yh + bb * li, o.frob + bb * g, o.col_pole + (size_t)b * g,

@@ -142,3 +142,20 @@ def test_gpu_refuses_family_without_device_path():
     with pytest.raises(C.CrError, match="no device path") as e:
         C.cr_frobenius_batch(fam, [7], [[1] * nco])
     assert e.value.status == C.CR_EINVAL
+
+
+@pytest.mark.gpu
+def test_gpu_rejects_a_threefold_that_is_not_s_smooth():
+    """The first candidate of the workload's hypersurface 17 (over F_11) is not
+    S-smooth for S = {x_4} (the host check says so): in a batch with the stored
+    golden it gets CR_ENOT_S_SMOOTH from the device elimination of J_S, and
+    the golden item's bits are unchanged."""
+    fam = C.family(5, 3, s_mask=1 << 4)
+    p, gen = workload.stream("cubic_threefolds_mixed", 17)
+    bad = next(gen)
+    assert p == 11 and not C.cr_check_smooth(fam, p, bad)
+    g = golden()
+    res = C.cr_frobenius_batch(fam, [g["p"], p], [g["coeffs"], bad], raise_on_error=False)
+    assert list(res["item_status"]) == [C.CR_OK, C.CR_ENOT_S_SMOOTH]
+    assert [[int(x) for x in row] for row in res["scaled"][0]] == [[int(x) for x in row] for row in g["scaled"]]
+    assert res["lpoly"][0] == [int(x) for x in g["lpoly"]]
