@@ -339,6 +339,13 @@ static int rank_mod_p(std::vector<int> a, int rows, int cols, int p) {
 // Non-pivot columns of the row-echelon form mod p of a (rows x cols) matrix:
 // column c is a pivot iff it is not a combination of columns 0..c-1.
 static std::vector<int> nonpivot_columns_mod_p(std::vector<int> a, int rows, int cols, int p) {
+    // Lazy reduction: a row below the pivots only accumulates g * (pivot row)
+    // terms (g < p, pivot entries reduced below p), at most one per pivot,
+    // so its entries stay below min(rows, cols) p^2 + p < 2^31 for the sizes
+    // here and are reduced mod p only where they are tested or become a
+    // pivot row.  The zero pattern mod p, and so the pivot columns, is that
+    // of the reduced elimination.
+    for (int &x : a) x = ((x % p) + p) % p;
     std::vector<int> out;
     int rank = 0;
     for (int c = 0; c < cols; c++) {
@@ -354,14 +361,17 @@ static std::vector<int> nonpivot_columns_mod_p(std::vector<int> a, int rows, int
         }
         if (sel != rank)
             for (int k = 0; k < cols; k++) std::swap(a[(size_t)sel * cols + k], a[(size_t)rank * cols + k]);
+        int *pr = &a[(size_t)rank * cols];
+        for (int k = c; k < cols; k++) pr[k] %= p;
         int inv = 1;
-        while ((a[(size_t)rank * cols + c] * inv) % p != 1) inv++;
-        for (int k = c; k < cols; k++) a[(size_t)rank * cols + k] = a[(size_t)rank * cols + k] * inv % p;
+        while ((pr[c] * inv) % p != 1) inv++;
+        for (int k = c; k < cols; k++) pr[k] = pr[k] * inv % p;
         for (int r = rank + 1; r < rows; r++) {
-            int f = a[(size_t)r * cols + c] % p;
+            int *ro = &a[(size_t)r * cols];
+            const int f = ro[c] % p;
             if (!f) continue;
-            for (int k = c; k < cols; k++)
-                a[(size_t)r * cols + k] = ((a[(size_t)r * cols + k] - f * a[(size_t)rank * cols + k]) % p + p) % p;
+            const int g = p - f;  // ro - f pr = ro + (p - f) pr (mod p)
+            for (int k = c; k < cols; k++) ro[k] += g * pr[k];
         }
         rank++;
     }
